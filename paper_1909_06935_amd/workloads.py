@@ -1,0 +1,323 @@
+"""Seeded synthetic inputs shared by the GPU path, the oracle and the tests.
+
+This module only draws random numbers and packs bit strings.  It contains
+none of the method's arithmetic: no matrix elements, no overlaps, no local
+energies.  Integral tensors, selected-CI determinant sets, strongly
+contracted class coefficients and initial walker determinants are produced
+here from seeds (numpy PCG64).  A reference wave function that must be an
+eigenvector (the exact CAS ground state) is not computed here; it is read
+from a file written by the oracle's reference script.
+
+Conventions (used everywhere in this repository)
+------------------------------------------------
+* Spatial orbitals are ordered [core | active | virtual], N = n_core +
+  n_act + n_virt.
+* A determinant is two spin strings (alpha, then beta).  Each spin string is
+  ``words = ceil(N / 64)`` little-endian uint64 words; bit i of word w is
+  orbital 64*w + i.  Arrays of determinants have shape ``[n, 2, words]``.
+* Strongly contracted classes (the subspaces S_l^(k) of the paper's Theory
+  section, l = occupied virtual spin-orbitals): class 0 is the active space;
+  a virtual spin-orbital is s = a + sigma*V (a = virtual index, sigma = 0 for
+  alpha, 1 for beta); one virtual electron -> id 1 + s; two virtual
+  electrons s1 < s2 -> id 1 + 2V + s1*(2V) - s1*(s1+1)/2 + (s2 - s1 - 1).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import os
+from typing import Optional
+
+import numpy as np
+
+DATA_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data")
+
+
+@dataclasses.dataclass
+class Space:
+    n_orb: int
+    n_core: int
+    n_act: int
+    n_elec_a: int
+    n_elec_b: int
+
+    @property
+    def n_virt(self) -> int:
+        return self.n_orb - self.n_core - self.n_act
+
+    @property
+    def words(self) -> int:
+        return (self.n_orb + 63) // 64
+
+    @property
+    def n_classes(self) -> int:
+        v2 = 2 * self.n_virt
+        return 1 + v2 + v2 * (v2 - 1) // 2
+
+    @property
+    def act_a(self) -> int:
+        return self.n_elec_a - self.n_core
+
+    @property
+    def act_b(self) -> int:
+        return self.n_elec_b - self.n_core
+
+
+@dataclasses.dataclass
+class Problem:
+    """Everything one sampling run needs (all host numpy arrays)."""
+    name: str
+    space: Space
+    h1: np.ndarray            # [N, N] symmetric
+    chol: np.ndarray          # [L, N, N] symmetric slices; (pq|rs) = sum_L B_pq B_rs
+    e_const: float
+    ref_dets: np.ndarray      # [n_det, 2, words] uint64, sorted unique
+    ref_coeff: np.ndarray     # [n_det] float64
+    c0: float
+    c_cls: np.ndarray         # [n_classes - 1] float64 (class 1 .. n_classes-1)
+    eps_virt: Optional[np.ndarray] = None
+    e0_ref: Optional[float] = None
+    n_walkers: int = 256
+    n_steps: int = 1000
+    burn_in: int = 100
+    seed_walk: int = 0
+
+
+# ---------------------------------------------------------------------------
+# bit-string helpers (packing only)
+# ---------------------------------------------------------------------------
+
+def pack_det(space: Space, occ_a, occ_b) -> np.ndarray:
+    """Pack occupied spatial orbital lists into a [2, words] uint64 array."""
+    out = np.zeros((2, space.words), dtype=np.uint64)
+    for s, occ in enumerate((occ_a, occ_b)):
+        for p in occ:
+            out[s, p // 64] |= np.uint64(1) << np.uint64(p % 64)
+    return out
+
+
+def unpack_det(space: Space, det: np.ndarray):
+    """Return (alpha occupied list, beta occupied list) of spatial orbitals."""
+    res = []
+    for s in range(2):
+        occ = []
+        for p in range(space.n_orb):
+            if (int(det[s, p // 64]) >> (p % 64)) & 1:
+                occ.append(p)
+        res.append(occ)
+    return res[0], res[1]
+
+
+def active_strings(space: Space, n_el: int):
+    """All active-space occupation lists with n_el electrons (lexicographic)."""
+    import itertools
+    base = space.n_core
+    return [tuple(base + i for i in c) for c in itertools.combinations(range(space.n_act), n_el)]
+
+
+def cas_dets(space: Space) -> np.ndarray:
+    """Every determinant of the complete active space, core doubly occupied."""
+    core = list(range(space.n_core))
+    sa = active_strings(space, space.act_a)
+    sb = active_strings(space, space.act_b)
+    out = np.zeros((len(sa) * len(sb), 2, space.words), dtype=np.uint64)
+    k = 0
+    for a in sa:
+        for b in sb:
+            out[k] = pack_det(space, core + list(a), core + list(b))
+            k += 1
+    return out
+
+
+def sort_dets(dets: np.ndarray, coeff: Optional[np.ndarray] = None):
+    """Sort determinants lexicographically by (alpha words, beta words), last word most significant."""
+    n = dets.shape[0]
+    flat = dets.reshape(n, -1)
+    keys = [flat[:, i] for i in range(flat.shape[1])]   # lexsort: last key is primary
+    order = np.lexsort(keys)
+    if coeff is None:
+        return dets[order]
+    return dets[order], coeff[order]
+
+
+# ---------------------------------------------------------------------------
+# integrals (BASELINE generator: graded h1 diagonal, low-rank Gaussian ERI)
+# ---------------------------------------------------------------------------
+
+def make_integrals(space: Space, rank: int, seed: int, sigma: float = 0.1):
+    """h1: symmetric, off-diagonal N(0, sigma), diagonal core -2.0, active
+    linspace(-0.5, 0.5), virtual linspace(1, 3).  B^L: symmetric with upper
+    triangle (incl. diagonal) N(0, sigma).  (pq|rs) = sum_L B^L_pq B^L_rs has
+    the 8-fold permutational symmetry of real orbitals."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = space.n_orb
+    h1 = rng.normal(0.0, sigma, size=(n, n))
+    h1 = np.triu(h1, 1)
+    h1 = h1 + h1.T
+    diag = np.concatenate([
+        np.full(space.n_core, -2.0),
+        np.linspace(-0.5, 0.5, space.n_act) if space.n_act > 1 else np.zeros(space.n_act),
+        np.linspace(1.0, 3.0, space.n_virt) if space.n_virt > 1 else np.full(space.n_virt, 1.0),
+    ])
+    h1[np.diag_indices(n)] = diag
+    iu = np.triu_indices(n)
+    chol = np.zeros((rank, n, n))
+    for L in range(rank):
+        b = np.zeros((n, n))
+        b[iu] = rng.normal(0.0, sigma, size=len(iu[0]))
+        chol[L] = b + np.triu(b, 1).T
+    return h1, chol
+
+
+def dense_eri(chol: np.ndarray) -> np.ndarray:
+    """(pq|rs) = sum_L B_pq B_rs as a dense [N,N,N,N] array (a plain tensor product)."""
+    n = chol.shape[1]
+    b = chol.reshape(chol.shape[0], n * n)
+    return (b.T @ b).reshape(n, n, n, n)
+
+
+# ---------------------------------------------------------------------------
+# reference determinant sets
+# ---------------------------------------------------------------------------
+
+def make_sci_reference(space: Space, n_det: int, seed: int, max_level: int = 6):
+    """Synthetic selected-CI reference: the aufbau determinant plus determinants
+    sampled by excitation level k ~ U{1..max_level}; k_alpha ~ Binomial(k, 1/2)
+    clipped to what each spin string allows; holes and particles uniform per
+    spin; duplicates rejected.  Coefficients N(0,1) * exp(-k), normalised,
+    the aufbau coefficient set to 1 before normalisation."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    na, nb, A, C = space.act_a, space.act_b, space.n_act, space.n_core
+    seen = {}
+    auf_a = tuple(range(na))
+    auf_b = tuple(range(nb))
+    seen[(auf_a, auf_b)] = (0, 1.0)
+    max_a = min(na, A - na)
+    max_b = min(nb, A - nb)
+    if n_det > math.comb(A, na) * math.comb(A, nb):
+        raise ValueError("more determinants requested than the active space holds")
+    while len(seen) < n_det:
+        k = int(rng.integers(1, max_level + 1))
+        ka = int(rng.binomial(k, 0.5))
+        ka = max(k - max_b, min(ka, max_a))
+        kb = k - ka
+        if kb < 0 or kb > max_b or ka < 0 or ka > max_a:
+            continue
+        strings = []
+        for n_el, kk in ((na, ka), (nb, kb)):
+            occ = np.arange(n_el)
+            virt = np.arange(n_el, A)
+            holes = rng.choice(occ, size=kk, replace=False) if kk else np.array([], dtype=int)
+            parts = rng.choice(virt, size=kk, replace=False) if kk else np.array([], dtype=int)
+            s = sorted(set(occ.tolist()) - set(holes.tolist()) | set(parts.tolist()))
+            strings.append(tuple(s))
+        key = (strings[0], strings[1])
+        if key in seen:
+            continue
+        seen[key] = (k, float(rng.normal()) * math.exp(-k))
+    dets = np.zeros((len(seen), 2, space.words), dtype=np.uint64)
+    coeff = np.zeros(len(seen))
+    core = list(range(C))
+    for i, ((sa, sb), (_k, c)) in enumerate(seen.items()):
+        dets[i] = pack_det(space, core + [C + x for x in sa], core + [C + x for x in sb])
+        coeff[i] = c
+    coeff /= np.linalg.norm(coeff)
+    return sort_dets(dets, coeff)
+
+
+def make_class_coeffs(space: Space, seed: int, c0: float = 1.0):
+    """Sampling-wave-function coefficients: c0 about ten times the others,
+    c_l = s_l * 0.1 * (0.5 + U[0,1)), s_l = +-1, never zero."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = space.n_classes - 1
+    sign = np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    mag = 0.1 * (0.5 + rng.random(n))
+    return c0, sign * mag
+
+
+def draw_walkers(ref_dets: np.ndarray, ref_coeff: np.ndarray, n_walkers: int, seed: int) -> np.ndarray:
+    """Initial walkers drawn from the reference with probability c_d^2 / sum c^2."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    p = ref_coeff ** 2
+    p = p / p.sum()
+    idx = rng.choice(len(p), size=n_walkers, p=p)
+    return np.ascontiguousarray(ref_dets[idx])
+
+
+# ---------------------------------------------------------------------------
+# named workloads
+# ---------------------------------------------------------------------------
+
+CONFIGS = {
+    # name: (N, core, act, elec, chol rank, walkers, steps, burn-in)
+    "cfg1": dict(n_orb=12, n_core=2, n_act=4, n_elec=8, rank=24, walkers=256, steps=1000, burn_in=100),
+    # 16 electrons: 4 doubly occupied core orbitals + 8 active electrons (CAS(8,8))
+    "cfg2": dict(n_orb=40, n_core=4, n_act=8, n_elec=16, rank=80, walkers=16384, steps=10000, burn_in=500),
+    "cfg3": dict(n_orb=100, n_core=10, n_act=14, n_elec=34, rank=200, walkers=65536, steps=1000, burn_in=200),
+}
+CONFIG_INDEX = {"cfg1": 1, "cfg2": 2, "cfg3": 3}
+
+
+def config_space(name: str) -> Space:
+    c = CONFIGS[name]
+    ne = c["n_elec"]
+    return Space(c["n_orb"], c["n_core"], c["n_act"], ne // 2, ne // 2)
+
+
+def seeds(name: str):
+    k = CONFIG_INDEX[name]
+    return dict(seed_int=1000 * k + 1, seed_ref=1000 * k + 2, seed_coef=1000 * k + 3, seed_walk=1000 * k + 4)
+
+
+def reference_file(name: str) -> str:
+    return os.path.join(DATA_DIR, f"{name}_reference.npz")
+
+
+def load_reference_file(name: str):
+    """Reference written by the oracle's reference script (exact CAS ground
+    state, truncated and renormalised for the 40-orbital workload)."""
+    path = reference_file(name)
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} missing: run `python oracle/make_references.py`")
+    z = np.load(path, allow_pickle=False)
+    return z["dets"].astype(np.uint64), z["coeff"].astype(np.float64)
+
+
+def make_problem(name: str, reference: Optional[tuple] = None, n_walkers: Optional[int] = None) -> Problem:
+    c = CONFIGS[name]
+    sp = config_space(name)
+    sd = seeds(name)
+    h1, chol = make_integrals(sp, c["rank"], sd["seed_int"])
+    if reference is not None:
+        dets, coeff = reference
+    elif name == "cfg3":
+        dets, coeff = make_sci_reference(sp, 50000, sd["seed_ref"])
+    else:
+        dets, coeff = load_reference_file(name)
+    c0, ccls = make_class_coeffs(sp, sd["seed_coef"])
+    return Problem(name=name, space=sp, h1=h1, chol=chol, e_const=0.0,
+                   ref_dets=dets, ref_coeff=coeff, c0=c0, c_cls=ccls,
+                   n_walkers=n_walkers or c["walkers"], n_steps=c["steps"],
+                   burn_in=c["burn_in"], seed_walk=sd["seed_walk"])
+
+
+def tiny_space(n_core: int, n_act: int, n_virt: int, act_a: int, act_b: int) -> Space:
+    return Space(n_core + n_act + n_virt, n_core, n_act, n_core + act_a, n_core + act_b)
+
+
+def make_tiny_problem(space: Space, seed: int, rank: int = 6, ref_fraction: float = 1.0,
+                      coeff_seed: Optional[int] = None) -> Problem:
+    """Small system for brute-force checks: random integrals, a random (not
+    eigen) reference over a random subset of the CAS, random class coefficients."""
+    h1, chol = make_integrals(space, rank, seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 17))
+    dets = cas_dets(space)
+    keep = rng.random(len(dets)) < ref_fraction
+    if not keep.any():
+        keep[0] = True
+    dets = dets[keep]
+    coeff = rng.normal(size=len(dets))
+    dets, coeff = sort_dets(dets, coeff)
+    c0, ccls = make_class_coeffs(space, coeff_seed if coeff_seed is not None else seed + 3)
+    return Problem(name="tiny", space=space, h1=h1, chol=chol, e_const=0.25,
+                   ref_dets=dets, ref_coeff=coeff, c0=c0, c_cls=ccls)
