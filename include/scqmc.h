@@ -1,0 +1,187 @@
+/*
+ * scqmc.h -- C ABI of the MI355X (gfx950) stochastic SC-MRCI / SC-NEVPT2
+ * local-energy engine.
+ *
+ * Method: Mahajan, Blunt, Sabzevari, Sharma, "Multireference configuration
+ * interaction and perturbation theory without reduced density matrices"
+ * (arXiv:1909.06935).  The library samples the strongly contracted (SC) wave
+ * function  psi_SC = sum_{k,l} c_l^(k) |psi_l^(k)>,  |psi_l^(k)> = P_l^(k) H |phi0>
+ * (Theory, "Overview of contraction schemes"; the state from S_0^(0) is phi0
+ * itself) with a rejection-free continuous-time walk over Slater determinants
+ * ("SC-MRCI(s)"), evaluating for every walker the local energy of eq:locE and,
+ * in NEVPT2 mode, the Dyall-Hamiltonian local energy needed by eq:nevpt.
+ *
+ * Conventions
+ *  - Spatial orbitals are ordered [core | active | virtual]; N <= 128,
+ *    n_act <= 32, at most 2*n_virt <= 65534 virtual spin-orbitals.
+ *  - A determinant is two spin strings, alpha then beta, each of
+ *    words = ceil(N/64) little-endian uint64 words; bit i of word w is orbital
+ *    64*w + i.  Arrays of determinants are [n][2][words].
+ *  - Core orbitals are doubly occupied in every determinant the method uses
+ *    (frozen core, "Implementation" section); at most two electrons sit in
+ *    virtual orbitals (the first-order interacting space).
+ *  - Class (the subspace S_l^(k), l = occupied virtual spin-orbitals): 0 for
+ *    the active space; virtual spin-orbital s = a + sigma*V (a in [0,V),
+ *    sigma = 0 alpha / 1 beta); one virtual electron: 1 + s; two, s1 < s2:
+ *    1 + 2V + s1*2V - s1*(s1+1)/2 + (s2 - s1 - 1).  n_classes = 1 + 2V + C(2V,2).
+ *  - Hamiltonian  H = e_const + sum h_pq a+_p a_q + 1/2 sum (pq|rs) a+_p a+_r a_s a_q
+ *    (chemist notation, real orbitals, 8-fold symmetric (pq|rs)).
+ *  - Phases: a single p->q has sign <m|a+_q a_p|n>; a double removing P1<P2
+ *    and adding Q1<Q2 (spin-orbital order: all alpha, then all beta) has sign
+ *    <m|a+_Q1 a+_Q2 a_P2 a_P1|n>.
+ *
+ * Ownership: host arrays are read during the call and copied; the library
+ * keeps no caller pointer.  Device pointers (eval_snapshot) must live on the
+ * context's device and are written asynchronously on the context's stream.
+ * Errors: every function returns scqmc_status; SCQMC_OK == 0.  The message of
+ * the last failure on a context is scqmc_last_error().  No exception crosses
+ * the ABI.  One context per host thread; contexts share nothing.
+ *
+ * Call order: set_space -> set_integrals_* -> set_reference -> set_sc_coeffs
+ * -> [set_dyall] -> [set_options] -> init_walkers -> sample / read_* ...
+ * Calling out of order returns SCQMC_E_STATE.
+ */
+#ifndef SCQMC_H
+#define SCQMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SCQMC_OK = 0,
+    SCQMC_E_INVALID_ARG = -1,  /* bad size, bad determinant, wrong length, ... */
+    SCQMC_E_STATE = -2,        /* called out of order */
+    SCQMC_E_UNSUPPORTED = -3,  /* outside the supported sizes */
+    SCQMC_E_OOM = -4,          /* device allocation failed */
+    SCQMC_E_DEVICE = -5,       /* HIP runtime error */
+    SCQMC_E_NUMERIC = -6       /* non-finite input, or a non-finite / zero-rate walker */
+} scqmc_status;
+
+typedef struct scqmc_ctx scqmc_ctx;
+
+typedef struct {
+    int32_t n_orb, n_core, n_act;
+    int32_t n_elec_a, n_elec_b;   /* total alpha / beta electrons (core included) */
+} scqmc_space;
+
+typedef struct {
+    double eps_screen;    /* doubles with |<rs||pq>| <= eps_screen are left out of the
+                             neighbour set ("heat-bath" screening, Implementation
+                             section); 0 = keep every double */
+    int32_t mode;         /* 0: local energy (SC-MRCI); 1: also the Dyall local energy and
+                             the per-class NEVPT2 sums of eq:nevpt (needs set_dyall) */
+    int32_t precision;    /* 0: FP64 (the only form implemented; others -> UNSUPPORTED) */
+    int64_t burn_in;      /* global step index from which estimators accumulate */
+    int64_t block_len;    /* steps per kernel launch inside scqmc_sample (0 = all) */
+} scqmc_options;
+
+typedef struct {
+    double e_var, e_var_err;    /* eq:vmc: sum t E_L / sum t, delete-one jackknife over walkers */
+    double a0_sq, a0_sq_err;    /* CAS residence fraction (Davidson section) */
+    double e_ref;               /* E_0^(0) as given to set_dyall (0 if not given) */
+    double davidson;            /* (1 - a0^2)(e_var - e_ref), Davidson correction equation */
+    double e2, e2_err;          /* SC-NEVPT2 E^(2) (eq:nevpt2e2) from the sampled sums; error
+                                   from the jackknife over walker groups is not available
+                                   per class, e2_err is NaN */
+    int64_t n_steps_accumulated, n_walkers;
+} scqmc_estimates;
+
+/* Create a context on HIP device `device`.  hip_stream: a hipStream_t to
+ * enqueue on, or NULL for a stream the context creates and owns. */
+scqmc_status scqmc_create(int device, void *hip_stream, scqmc_ctx **out);
+void scqmc_destroy(scqmc_ctx *ctx);
+const char *scqmc_last_error(const scqmc_ctx *ctx);
+
+/* Orbital partition and electron counts.  Requires n_core <= n_elec_a,b,
+ * n_elec_a,b - n_core < n_act (a hole must exist), N <= 128, n_act <= 32. */
+scqmc_status scqmc_set_space(scqmc_ctx *ctx, const scqmc_space *space);
+
+/* Integrals in Cholesky form: h1 [N*N] (symmetric), chol [n_chol][N][N]
+ * (each slice symmetric), (pq|rs) = sum_L chol[L][p][q] chol[L][r][s].
+ * The library forms the core-folded one-body operator
+ * h_eff_pq = h_pq + sum_i (2(pq|ii) - (pi|iq)), the core energy, and the
+ * two-electron integrals over active+virtual orbitals on the device. */
+scqmc_status scqmc_set_integrals_chol(scqmc_ctx *ctx, const double *h1, const double *chol, int32_t n_chol,
+                                      double e_const);
+/* Same with a dense [N^4] chemist-notation tensor (pq|rs) at eri[((p*N+q)*N+r)*N+s]. */
+scqmc_status scqmc_set_integrals_dense(scqmc_ctx *ctx, const double *h1, const double *eri, double e_const);
+
+/* Active-space reference phi0 (selected CI / CASCI, the "Implementation"
+ * section): n_det determinants [n_det][2][words] and coefficients.  Each
+ * determinant must have a full core, no virtual electron and the right
+ * electron counts; duplicates are rejected.  phi0 need not be normalised.
+ * The library builds a device hash table of the determinants (constant-time
+ * overlap, "SC-MRCI(s)") and two derived tables that list, for every
+ * determinant with one or two active electrons removed, the reference
+ * determinants it came from. */
+scqmc_status scqmc_set_reference(scqmc_ctx *ctx, int64_t n_det, const uint64_t *dets, const double *coeff);
+
+/* SC coefficients: c0 for phi0 and c_cls[n-1] for classes 1..n_classes-1
+ * (n must equal n_classes).  Zero coefficients are allowed (the class is then
+ * never visited). */
+scqmc_status scqmc_set_sc_coeffs(scqmc_ctx *ctx, double c0, const double *c_cls, int64_t n);
+
+/* Dyall Hamiltonian of "SC-NEVPT2(s)": virtual orbital energies eps_virt[V]
+ * (the orbitals are taken as the semicanonical virtuals, so the virtual part
+ * of H_D is diagonal) and E_0^(0).  H_D = sum_a eps_a n_a + H_0, where H_0 is
+ * the core-averaged active-space Hamiltonian (e_const and core energy
+ * included, so <phi0|H_D|phi0> = <phi0|H|phi0>).  Required for mode 1. */
+scqmc_status scqmc_set_dyall(scqmc_ctx *ctx, const double *eps_virt, double e0_ref);
+
+scqmc_status scqmc_set_options(scqmc_ctx *ctx, const scqmc_options *opt);
+
+/* Place n_walkers walkers on the given determinants (host [W][2][words]); the
+ * global walker id of row w is w.  seed keys the Philox4x32-10 counter
+ * generator.  Resets the step counter and every accumulator.  Fails with
+ * INVALID_ARG if a determinant is outside the allowed space or has psi = 0. */
+scqmc_status scqmc_init_walkers(scqmc_ctx *ctx, int64_t n_walkers, const uint64_t *dets, uint64_t seed);
+
+/* Advance every walker by n_steps continuous-time steps (enqueued on the
+ * context stream; returns after launch).  Each step evaluates E_L (and in
+ * mode 1 the Dyall local energy), the rates |psi(m)/psi(n)| over the
+ * neighbour set, accumulates the estimators with residence weight
+ * t = 1/sum of rates once the global step index reaches burn_in, and moves
+ * the walker by the two-level first-reaction method (group of neighbours
+ * sharing an active part, then one neighbour within it). */
+scqmc_status scqmc_sample(scqmc_ctx *ctx, int64_t n_steps);
+scqmc_status scqmc_synchronize(scqmc_ctx *ctx);
+
+/* Host finalisation of the accumulated sums (synchronises). */
+scqmc_status scqmc_read_estimates(scqmc_ctx *ctx, scqmc_estimates *out);
+/* Per-class sums (n == n_classes): t_l = sum t, te_l = sum t E_L,
+ * n_l = sum t / c_l^2, d_l = sum t E_D,L / c_l^2 (synchronises). */
+scqmc_status scqmc_read_class_sums(scqmc_ctx *ctx, double *n_l, double *d_l, double *t_l, double *te_l, int64_t n);
+/* Per-walker sums (n == n_walkers): sum t, sum t E_L, sum t [class 0] (synchronises). */
+scqmc_status scqmc_read_walker_sums(scqmc_ctx *ctx, double *sum_t, double *sum_te, double *sum_t0, int64_t n);
+/* Current walker determinants [n][2][words] and psi(n) (synchronises). */
+scqmc_status scqmc_read_walkers(scqmc_ctx *ctx, uint64_t *dets, double *psi, int64_t n);
+/* Steps taken since init_walkers and the count of walker-steps whose rates
+ * summed to zero or whose local energy was not finite. */
+scqmc_status scqmc_read_counters(scqmc_ctx *ctx, int64_t *steps, int64_t *bad_steps);
+
+/* Parity / debug.  Local energies of n determinants d_dets [n][2][words]
+ * (device) without moving: E_L, psi, Gamma = sum_m |psi(m)/psi(n)|, the Dyall
+ * local energy (mode 1, NaN for class 0; pass NULL to skip) and the class.
+ * A determinant outside the allowed space or with psi = 0 gets NaN. */
+scqmc_status scqmc_eval_snapshot(scqmc_ctx *ctx, int64_t n, const uint64_t *d_dets, double *d_eloc, double *d_psi,
+                                 double *d_gamma, double *d_eloc_dyall, int32_t *d_class);
+/* Neighbour set M(n) of one host determinant: up to cap entries of
+ * determinant [2][words], phase (+-1), <m|H|n>, psi(m) (host arrays);
+ * *out_count receives |M(n)|.  Order is unspecified. */
+scqmc_status scqmc_debug_neighbors(scqmc_ctx *ctx, const uint64_t *det, int64_t cap, uint64_t *out_dets,
+                                   int8_t *out_phase, double *out_hnm, double *out_psi, int64_t *out_count);
+
+/* Checkpoint: walker state, step counter, seed and every accumulator, as an
+ * opaque byte buffer (host).  *used receives the size; cap too small ->
+ * INVALID_ARG with *used set.  load_state requires the same space, reference
+ * and options; a walk resumed from it continues bit for bit. */
+scqmc_status scqmc_save_state(scqmc_ctx *ctx, void *buf, int64_t cap, int64_t *used);
+scqmc_status scqmc_load_state(scqmc_ctx *ctx, const void *buf, int64_t len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCQMC_H */

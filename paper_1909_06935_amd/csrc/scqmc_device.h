@@ -1,0 +1,227 @@
+// scqmc_device.h -- device-side data structures and helpers of the gfx950
+// local-energy engine (stochastic SC-MRCI / SC-NEVPT2, arXiv:1909.06935).
+//
+// Internal representation
+//   * non-core spin-orbital g = sigma * Np + idx, idx in [0, Np) with
+//     Np = A + V (active orbitals first, then virtual); g order = the
+//     determinant's creation-operator order restricted to non-core orbitals
+//     (all alpha, then all beta).  Core orbitals are always doubly occupied
+//     and contribute only through the folded one-body operator and E_core.
+//   * active code c = sigma * 32 + t (t in [0, A)): bit c of a 64-bit key.
+//   * virtual code s = sigma * V + a: class labels (the subspaces S_l^(k) of
+//     the paper's Theory section).
+//   * a walker is (active key, packed virtual codes): two 16-bit codes,
+//     ascending, 0xFFFF when absent.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define SCQ_EMPTY_KEY 0xFFFFFFFFFFFFFFFFull
+#define SCQ_NOVIRT 0xFFFFu
+
+struct DevTable {
+    const unsigned long long *keys;  // [cap], SCQ_EMPTY_KEY = free slot
+    const uint2 *offcnt;             // [cap]: (offset, count) into codes / vals
+    const uint32_t *codes;           // entry codes (ytab: t; xtab: t<<6 | u; ref: 0)
+    const double *vals;              // entry reference coefficients
+    unsigned long long mask;         // cap - 1 (cap a power of two)
+};
+
+struct DevProblem {
+    int A, V, Np;           // active, virtual, non-core orbital counts
+    int nea, neb;           // active-space electrons per spin (n_elec - n_core)
+    int mode;               // 0: E_L; 1: + Dyall local energy
+    long long ncls;         // number of classes
+    double e_core;          // e_const + core energy
+    double eps_screen;      // doubles with |<rs||pq>| <= eps are left out (0: keep all)
+    const double *heff;     // [Np*Np] core-folded one-body operator
+    const double *eri;      // [Np^4] (pq|rs) over non-core orbitals
+    const double *ccls;     // [ncls] SC coefficients, c0 at index 0
+    const double *eps;      // [V] Dyall virtual orbital energies (mode 1)
+    DevTable ref, ytab, xtab;
+    unsigned long long seed;
+};
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int popc32(uint32_t x) { return __popc(x); }
+__device__ __forceinline__ int popc64(uint64_t x) { return __popcll(x); }
+
+// MurmurHash3 64-bit finaliser (Appleby), used as the table hash.
+__device__ __forceinline__ unsigned long long scq_hash(unsigned long long k) {
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdull;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ull;
+    k ^= k >> 33;
+    return k;
+}
+
+// Open-addressing lookup (linear probing).  Returns the (offset, count) of
+// the key's entry list, count 0 when absent.
+__device__ __forceinline__ uint2 table_find(const DevTable &t, unsigned long long key) {
+    unsigned long long slot = scq_hash(key) & t.mask;
+    while (true) {
+        unsigned long long k = t.keys[slot];
+        if (k == key) return t.offcnt[slot];
+        if (k == SCQ_EMPTY_KEY) return make_uint2(0u, 0u);
+        slot = (slot + 1) & t.mask;
+    }
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; r++) {
+        if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        uint32_t hi0 = __umulhi(0xD2511F53u, c[0]), lo0 = 0xD2511F53u * c[0];
+        uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]), lo1 = 0xCD9E8D57u * c[2];
+        uint32_t y0 = hi1 ^ c[1] ^ k0, y2 = hi0 ^ c[3] ^ k1;
+        c[0] = y0; c[1] = lo1; c[2] = y2; c[3] = lo0;
+    }
+}
+
+// Exponential variate E = -log(U), U = (k+1) 2^-53, k = top 53 bits of the
+// first two Philox words; counter (walker, step | level<<31, a, b).
+__device__ __forceinline__ double exp_draw(unsigned long long seed, uint32_t walker, uint32_t step, uint32_t level,
+                                           uint32_t a, uint32_t b) {
+    uint32_t c[4] = {walker, (step & 0x7fffffffu) | (level << 31), a, b};
+    philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    unsigned long long k = ((((unsigned long long)c[0]) << 32) | (unsigned long long)c[1]) >> 11;
+    double u = (double)(k + 1ull) * 0x1.0p-53;
+    return -log(u);
+}
+
+__device__ __forceinline__ long long class_id1(int V, int s) { return 1 + s; }
+__device__ __forceinline__ long long class_id2(int V, int s1, int s2) {
+    long long V2 = 2LL * V;
+    return 1 + V2 + (long long)s1 * V2 - (long long)s1 * (s1 + 1) / 2 + (s2 - s1 - 1);
+}
+
+// ---------------------------------------------------------------------------
+// determinants over non-core spin-orbitals
+// ---------------------------------------------------------------------------
+struct NDet {           // occupation: active key + up to two virtual electrons (g codes, ascending)
+    unsigned long long key;
+    int nv;
+    int vg[2];
+};
+
+__device__ __forceinline__ int g_of_active(const DevProblem &P, int c) { return (c >> 5) * P.Np + (c & 31); }
+__device__ __forceinline__ int g_of_virtual(const DevProblem &P, int s) {
+    int sg = s >= P.V;
+    return sg * P.Np + P.A + (s - sg * P.V);
+}
+__device__ __forceinline__ int g_spin(const DevProblem &P, int g) { return g >= P.Np; }
+__device__ __forceinline__ int g_idx(const DevProblem &P, int g) { return g >= P.Np ? g - P.Np : g; }
+
+// number of occupied non-core spin-orbitals of d below g (creation order)
+__device__ __forceinline__ int below(const DevProblem &P, const NDet &d, int g) {
+    int sg = g >= P.Np;
+    int idx = g - sg * P.Np;
+    uint32_t act = (uint32_t)(d.key >> (32 * sg));
+    int c = 0;
+    if (sg) {
+        c += popc32((uint32_t)d.key);
+        for (int i = 0; i < d.nv; i++) c += (d.vg[i] < P.Np);
+    }
+    if (idx < P.A) {
+        c += popc32(act & ((1u << idx) - 1u));
+    } else {
+        c += popc32(act);
+        for (int i = 0; i < d.nv; i++) c += (d.vg[i] >= sg * P.Np && d.vg[i] < g);
+    }
+    return c;
+}
+
+// sign of <m| a+_Q a_P |b>
+__device__ __forceinline__ double phase_single(const DevProblem &P, const NDet &b, int gP, int gQ) {
+    int e = below(P, b, gP) + below(P, b, gQ) - (gP < gQ ? 1 : 0);
+    return (e & 1) ? -1.0 : 1.0;
+}
+// sign of <m| a+_Q1 a+_Q2 a_P2 a_P1 |b>, P1 < P2 removed from b, Q1 < Q2 added
+__device__ __forceinline__ double phase_double(const DevProblem &P, const NDet &b, int P1, int P2, int Q1, int Q2) {
+    int e = below(P, b, P1);
+    e += below(P, b, P2) - (P1 < P2);
+    e += below(P, b, Q2) - (P1 < Q2) - (P2 < Q2);
+    e += below(P, b, Q1) - (P1 < Q1) - (P2 < Q1) + (Q2 < Q1);
+    return (e & 1) ? -1.0 : 1.0;
+}
+
+__device__ __forceinline__ double eri4(const DevProblem &P, int p, int q, int r, int s) {
+    unsigned Np = (unsigned)P.Np;
+    return P.eri[((p * Np + q) * Np + r) * Np + s];
+}
+// spin-orbital chemist integral (PQ|RS)
+__device__ __forceinline__ double seri(const DevProblem &P, int gP, int gQ, int gR, int gS) {
+    if (g_spin(P, gP) != g_spin(P, gQ) || g_spin(P, gR) != g_spin(P, gS)) return 0.0;
+    return eri4(P, g_idx(P, gP), g_idx(P, gQ), g_idx(P, gR), g_idx(P, gS));
+}
+// <Q1 Q2 || P1 P2> piece of a double: (Q1 P1|Q2 P2) - (Q1 P2|Q2 P1)
+__device__ __forceinline__ double double_elem(const DevProblem &P, int P1, int P2, int Q1, int Q2) {
+    return seri(P, Q1, P1, Q2, P2) - seri(P, Q1, P2, Q2, P1);
+}
+
+// one-body part of a single P -> Q from determinant b:
+// h_eff[Q][P] + sum_{J in b, J != P} [(QP|JJ) - (QJ|JP)]; with_virt = 0 drops
+// the virtual electrons from the sum (Dyall's H_0 acts on the active space only)
+__device__ __forceinline__ double single_elem(const DevProblem &P, const NDet &b, int gP, int gQ, bool with_virt) {
+    int p = g_idx(P, gP), q = g_idx(P, gQ), sp = g_spin(P, gP);
+    double v = P.heff[q * P.Np + p];
+    for (int s = 0; s < 2; s++) {
+        uint32_t act = (uint32_t)(b.key >> (32 * s));
+        while (act) {
+            int t = __ffs(act) - 1;
+            act &= act - 1u;
+            int gJ = s * P.Np + t;
+            if (gJ == gP) continue;
+            // (qp|jj) = (jj|pq) and (qj|jp) = (pj|jq): the lane-varying index goes last
+            double J = eri4(P, t, t, p, q);
+            double K = (s == sp) ? eri4(P, p, t, t, q) : 0.0;
+            v += J - K;
+        }
+    }
+    if (with_virt) {
+        for (int i = 0; i < b.nv; i++) {
+            int gJ = b.vg[i];
+            if (gJ == gP) continue;
+            int j = g_idx(P, gJ), s = g_spin(P, gJ);
+            double J = eri4(P, j, j, p, q);
+            double K = (s == sp) ? eri4(P, p, j, j, q) : 0.0;
+            v += J - K;
+        }
+    }
+    return v;
+}
+
+// diagonal <b|H|b> over non-core electrons plus E_core (with_virt = 0: the
+// active part only, i.e. Dyall's H_0 without the orbital-energy term)
+__device__ inline double diag_elem(const DevProblem &P, const NDet &b, bool with_virt) {
+    int gs[72];
+    int n = 0;
+    for (int s = 0; s < 2; s++) {
+        uint32_t act = (uint32_t)(b.key >> (32 * s));
+        while (act) {
+            int t = __ffs(act) - 1;
+            act &= act - 1u;
+            gs[n++] = s * P.Np + t;
+        }
+    }
+    if (with_virt)
+        for (int i = 0; i < b.nv; i++) gs[n++] = b.vg[i];
+    double v = P.e_core;
+    for (int i = 0; i < n; i++) {
+        int ii = g_idx(P, gs[i]);
+        v += P.heff[ii * P.Np + ii];
+    }
+    double two = 0.0;
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < n; j++) {
+            int ii = g_idx(P, gs[i]), jj = g_idx(P, gs[j]);
+            double J = eri4(P, ii, ii, jj, jj);
+            double K = g_spin(P, gs[i]) == g_spin(P, gs[j]) ? eri4(P, ii, jj, jj, ii) : 0.0;
+            two += J - K;
+        }
+    return v + 0.5 * two;
+}

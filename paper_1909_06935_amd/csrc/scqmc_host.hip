@@ -1,0 +1,819 @@
+// scqmc_host.hip -- host runtime behind the C ABI of include/scqmc.h.
+//
+// Owns device memory and the stream, validates every input on the host,
+// runs the setup kernels (integral blocks, core folding, reference tables)
+// and launches the walker kernels.  Finalisation of the sampled sums
+// (energy, jackknife error, a0^2, Davidson correction, E^(2)) is host FP64
+// on a handful of numbers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/scqmc.h"
+#include "scqmc_kernels.hip"
+
+namespace {
+
+struct DBuf {
+    void *p = nullptr;
+    size_t n = 0;
+    ~DBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    template <class T> T *as() const { return (T *)p; }
+};
+
+struct TableBufs {
+    DBuf keys, offcnt, codes, vals;
+    unsigned long long cap = 0;
+    DevTable view() const {
+        DevTable t;
+        t.keys = keys.as<unsigned long long>();
+        t.offcnt = offcnt.as<uint2>();
+        t.codes = codes.as<uint32_t>();
+        t.vals = vals.as<double>();
+        t.mask = cap ? cap - 1 : 0;
+        return t;
+    }
+};
+
+struct Status {
+    scqmc_status s;
+};
+
+}  // namespace
+
+struct scqmc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    bool has_space = false, has_ints = false, has_ref = false, has_coef = false, has_dyall = false,
+         has_walkers = false;
+    int N = 0, C = 0, A = 0, V = 0, Np = 0, words = 0, na = 0, nb = 0, nea = 0, neb = 0;
+    long long ncls = 0;
+    scqmc_options opt{0.0, 0, 0, 0, 0};
+    double e_core = 0.0, e0_ref = 0.0;
+    DBuf heff, eri, ccls, eps, refcoef;
+    TableBufs ref, ytab, xtab;
+    long long n_ref = 0;
+    std::vector<double> ccls_h, eps_h;
+    // walkers
+    long long W = 0, step = 0;
+    unsigned long long seed = 0;
+    DBuf wkey, wvirt, wpsi, wsum, cacc, bad;
+    // snapshot scratch
+    DBuf skey, svirt, svalid;
+};
+
+#define FAIL(ctx, code, msg)          \
+    do {                              \
+        (ctx)->err = (msg);           \
+        return (code);                \
+    } while (0)
+
+#define HIPCHK(ctx, call)                                                                  \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess) {                                                            \
+            (ctx)->err = std::string(#call) + ": " + hipGetErrorString(e_);                \
+            return e_ == hipErrorOutOfMemory ? SCQMC_E_OOM : SCQMC_E_DEVICE;               \
+        }                                                                                  \
+    } while (0)
+
+static scqmc_status dalloc(scqmc_ctx *ctx, DBuf &b, size_t bytes) {
+    b.release();
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        ctx->err = std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e);
+        return SCQMC_E_OOM;
+    }
+    b.n = bytes;
+    return SCQMC_OK;
+}
+
+#define TRY(x)                           \
+    do {                                 \
+        scqmc_status s_ = (x);           \
+        if (s_ != SCQMC_OK) return s_;   \
+    } while (0)
+
+static inline unsigned grid1(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+static DevProblem dev_problem(const scqmc_ctx *c) {
+    DevProblem P;
+    P.A = c->A;
+    P.V = c->V;
+    P.Np = c->Np;
+    P.nea = c->nea;
+    P.neb = c->neb;
+    P.mode = c->opt.mode;
+    P.ncls = c->ncls;
+    P.e_core = c->e_core;
+    P.eps_screen = c->opt.eps_screen;
+    P.heff = c->heff.as<double>();
+    P.eri = c->eri.as<double>();
+    P.ccls = c->ccls.as<double>();
+    P.eps = c->eps.as<double>();
+    P.ref = c->ref.view();
+    P.ytab = c->ytab.view();
+    P.xtab = c->xtab.view();
+    P.seed = c->seed;
+    return P;
+}
+
+static int lists_per_group(const scqmc_ctx *c) { return std::max(1, c->nea + c->neb); }
+
+// Host compaction of one full determinant: active key, packed virtual codes.
+// Returns false (with a reason) if it is outside the allowed space.
+static bool compact_host(const scqmc_ctx *c, const uint64_t *d, unsigned long long &key, unsigned &virt,
+                         std::string &why) {
+    key = 0;
+    int vc[3], nv = 0;
+    for (int s = 0; s < 2; s++) {
+        int cnt = 0;
+        for (int w = 0; w < c->words; w++) {
+            uint64_t word = d[s * c->words + w];
+            for (int b = 0; b < 64; b++) {
+                if (!((word >> b) & 1ull)) continue;
+                int p = 64 * w + b;
+                if (p >= c->N) { why = "bit beyond n_orb set"; return false; }
+                cnt++;
+                if (p >= c->C && p < c->C + c->A) key |= 1ull << (32 * s + p - c->C);
+                else if (p >= c->C + c->A) { if (nv < 3) vc[nv] = s * c->V + (p - c->C - c->A); nv++; }
+            }
+        }
+        for (int p = 0; p < c->C; p++)
+            if (!((d[s * c->words + (p >> 6)] >> (p & 63)) & 1ull)) { why = "core hole"; return false; }
+        if (cnt != (s == 0 ? c->na : c->nb)) { why = "wrong electron count"; return false; }
+    }
+    if (nv > 2) { why = "more than two virtual electrons"; return false; }
+    virt = (nv > 0 ? (unsigned)vc[0] : SCQ_NOVIRT) | ((nv > 1 ? (unsigned)vc[1] : SCQ_NOVIRT) << 16);
+    return true;
+}
+
+static void expand_host(const scqmc_ctx *c, unsigned long long key, unsigned virt, uint64_t *d) {
+    std::memset(d, 0, sizeof(uint64_t) * 2 * c->words);
+    auto set = [&](int s, int p) { d[s * c->words + (p >> 6)] |= 1ull << (p & 63); };
+    for (int s = 0; s < 2; s++) {
+        for (int p = 0; p < c->C; p++) set(s, p);
+        for (int t = 0; t < c->A; t++)
+            if ((key >> (32 * s + t)) & 1ull) set(s, c->C + t);
+    }
+    for (int i = 0; i < 2; i++) {
+        unsigned v = (virt >> (16 * i)) & 0xFFFFu;
+        if (v == SCQ_NOVIRT) continue;
+        int s = (int)v >= c->V;
+        set(s, c->C + c->A + (int)v - s * c->V);
+    }
+}
+
+static bool all_finite(const double *x, size_t n) {
+    for (size_t i = 0; i < n; i++)
+        if (!std::isfinite(x[i])) return false;
+    return true;
+}
+
+extern "C" {
+
+scqmc_status scqmc_create(int device, void *hip_stream, scqmc_ctx **out) {
+    if (!out) return SCQMC_E_INVALID_ARG;
+    *out = nullptr;
+    scqmc_ctx *c = new (std::nothrow) scqmc_ctx();
+    if (!c) return SCQMC_E_OOM;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        delete c;
+        return SCQMC_E_DEVICE;
+    }
+    c->device = device;
+    if (hipSetDevice(device) != hipSuccess) { delete c; return SCQMC_E_DEVICE; }
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) { delete c; return SCQMC_E_DEVICE; }
+        c->own_stream = true;
+    }
+    *out = c;
+    return SCQMC_OK;
+}
+
+void scqmc_destroy(scqmc_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+const char *scqmc_last_error(const scqmc_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+scqmc_status scqmc_set_space(scqmc_ctx *c, const scqmc_space *s) {
+    if (!c || !s) return SCQMC_E_INVALID_ARG;
+    if (s->n_orb <= 0 || s->n_core < 0 || s->n_act <= 0 || s->n_core + s->n_act > s->n_orb)
+        FAIL(c, SCQMC_E_INVALID_ARG, "bad orbital partition");
+    if (s->n_orb > 128 || s->n_act > 32) FAIL(c, SCQMC_E_UNSUPPORTED, "n_orb > 128 or n_act > 32");
+    int V = s->n_orb - s->n_core - s->n_act;
+    if (2 * V > 65534) FAIL(c, SCQMC_E_UNSUPPORTED, "too many virtual orbitals");
+    int nea = s->n_elec_a - s->n_core, neb = s->n_elec_b - s->n_core;
+    if (nea < 0 || neb < 0 || nea > s->n_act || neb > s->n_act)
+        FAIL(c, SCQMC_E_INVALID_ARG, "electron counts inconsistent with core / active sizes");
+    if (nea + neb == 0) FAIL(c, SCQMC_E_INVALID_ARG, "no active electron");
+    if (s->n_act == 32 && nea == 32 && neb == 32) FAIL(c, SCQMC_E_UNSUPPORTED, "active space completely filled");
+    if (nea + neb > 23) FAIL(c, SCQMC_E_UNSUPPORTED, "more than 23 active electrons");
+    c->N = s->n_orb; c->C = s->n_core; c->A = s->n_act; c->V = V; c->Np = s->n_act + V;
+    c->words = (s->n_orb + 63) / 64;
+    c->na = s->n_elec_a; c->nb = s->n_elec_b; c->nea = nea; c->neb = neb;
+    long long V2 = 2LL * V;
+    c->ncls = 1 + V2 + V2 * (V2 - 1) / 2;
+    c->has_space = true;
+    c->has_ints = c->has_ref = c->has_coef = c->has_dyall = c->has_walkers = false;
+    c->err.clear();
+    return SCQMC_OK;
+}
+
+static scqmc_status finish_integrals(scqmc_ctx *c, DBuf &full, DBuf &h1d, double e_const) {
+    long long Np4 = (long long)c->Np * c->Np * c->Np * c->Np;
+    TRY(dalloc(c, c->eri, sizeof(double) * Np4));
+    TRY(dalloc(c, c->heff, sizeof(double) * c->Np * c->Np));
+    DBuf ec;
+    TRY(dalloc(c, ec, sizeof(double)));
+    hipLaunchKernelGGL(k_noncore, dim3(grid1(std::max(Np4, (long long)c->Np * c->Np), 256)), dim3(256), 0, c->stream,
+                       full.as<double>(), h1d.as<double>(), c->N, c->C, c->eri.as<double>(), c->heff.as<double>());
+    hipLaunchKernelGGL(k_ecore, dim3(1), dim3(1), 0, c->stream, full.as<double>(), h1d.as<double>(), c->N, c->C,
+                       e_const, ec.as<double>());
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(&c->e_core, ec.p, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->has_ints = true;
+    return SCQMC_OK;
+}
+
+static bool symmetric_copy(const double *a, int n, std::vector<double> &out) {
+    out.assign(a, a + (size_t)n * n);
+    double mx = 0.0;
+    for (int i = 0; i < n * n; i++) mx = std::max(mx, std::fabs(a[i]));
+    for (int p = 0; p < n; p++)
+        for (int q = p + 1; q < n; q++) {
+            double x = a[p * n + q], y = a[q * n + p];
+            if (std::fabs(x - y) > 1e-10 * (1.0 + mx)) return false;
+            double m = 0.5 * (x + y);
+            out[p * n + q] = out[q * n + p] = m;
+        }
+    return true;
+}
+
+scqmc_status scqmc_set_integrals_chol(scqmc_ctx *c, const double *h1, const double *chol, int32_t n_chol,
+                                      double e_const) {
+    if (!c) return SCQMC_E_INVALID_ARG;
+    if (!c->has_space) FAIL(c, SCQMC_E_STATE, "set_space first");
+    if (!h1 || (!chol && n_chol > 0) || n_chol < 0) FAIL(c, SCQMC_E_INVALID_ARG, "null integral array");
+    int N = c->N;
+    long long N2 = (long long)N * N;
+    if (!std::isfinite(e_const) || !all_finite(h1, N2) || !all_finite(chol, (size_t)N2 * n_chol))
+        FAIL(c, SCQMC_E_NUMERIC, "non-finite integral");
+    std::vector<double> hs, Bs((size_t)N2 * std::max(n_chol, 1)), tmp;
+    if (!symmetric_copy(h1, N, hs)) FAIL(c, SCQMC_E_INVALID_ARG, "h1 not symmetric");
+    for (int l = 0; l < n_chol; l++) {
+        if (!symmetric_copy(chol + l * N2, N, tmp)) FAIL(c, SCQMC_E_INVALID_ARG, "Cholesky slice not symmetric");
+        std::copy(tmp.begin(), tmp.end(), Bs.begin() + l * N2);
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    DBuf Bd, h1d, full;
+    TRY(dalloc(c, Bd, sizeof(double) * N2 * std::max(n_chol, 1)));
+    TRY(dalloc(c, h1d, sizeof(double) * N2));
+    TRY(dalloc(c, full, sizeof(double) * N2 * N2));
+    HIPCHK(c, hipMemcpyAsync(Bd.p, Bs.data(), sizeof(double) * N2 * n_chol, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(h1d.p, hs.data(), sizeof(double) * N2, hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(k_eri_chol, dim3(grid1(N2 * N2, 256)), dim3(256), 0, c->stream, Bd.as<double>(), n_chol, N2,
+                       full.as<double>());
+    HIPCHK(c, hipGetLastError());
+    TRY(finish_integrals(c, full, h1d, e_const));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SCQMC_OK;
+}
+
+scqmc_status scqmc_set_integrals_dense(scqmc_ctx *c, const double *h1, const double *eri, double e_const) {
+    if (!c) return SCQMC_E_INVALID_ARG;
+    if (!c->has_space) FAIL(c, SCQMC_E_STATE, "set_space first");
+    if (!h1 || !eri) FAIL(c, SCQMC_E_INVALID_ARG, "null integral array");
+    int N = c->N;
+    long long N2 = (long long)N * N;
+    if (!std::isfinite(e_const) || !all_finite(h1, N2) || !all_finite(eri, (size_t)N2 * N2))
+        FAIL(c, SCQMC_E_NUMERIC, "non-finite integral");
+    std::vector<double> hs;
+    if (!symmetric_copy(h1, N, hs)) FAIL(c, SCQMC_E_INVALID_ARG, "h1 not symmetric");
+    HIPCHK(c, hipSetDevice(c->device));
+    DBuf h1d, full;
+    TRY(dalloc(c, h1d, sizeof(double) * N2));
+    TRY(dalloc(c, full, sizeof(double) * N2 * N2));
+    HIPCHK(c, hipMemcpyAsync(h1d.p, hs.data(), sizeof(double) * N2, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(full.p, eri, sizeof(double) * N2 * N2, hipMemcpyHostToDevice, c->stream));
+    TRY(finish_integrals(c, full, h1d, e_const));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SCQMC_OK;
+}
+
+static scqmc_status build_table(scqmc_ctx *c, int mode, const DBuf &rkeys, long long n, TableBufs &t) {
+    int ne = c->nea + c->neb;
+    long long per = mode == 0 ? 1 : mode == 1 ? ne : (long long)ne * (ne - 1) / 2;
+    long long M = n * per;
+    unsigned long long cap = 64;
+    while (cap < 2ull * (unsigned long long)std::max(M, 1LL)) cap <<= 1;
+    t.cap = cap;
+    DBuf ekeys, epay, cnt, off, cur, slot_of, tmp, total;
+    TRY(dalloc(c, ekeys, sizeof(unsigned long long) * M));
+    TRY(dalloc(c, epay, sizeof(unsigned long long) * M));
+    TRY(dalloc(c, cnt, sizeof(unsigned) * cap));
+    TRY(dalloc(c, off, sizeof(unsigned) * cap));
+    TRY(dalloc(c, cur, sizeof(unsigned) * cap));
+    TRY(dalloc(c, slot_of, sizeof(unsigned) * M));
+    TRY(dalloc(c, tmp, sizeof(unsigned long long) * M));
+    TRY(dalloc(c, total, sizeof(unsigned)));
+    TRY(dalloc(c, t.keys, sizeof(unsigned long long) * cap));
+    TRY(dalloc(c, t.offcnt, sizeof(uint2) * cap));
+    TRY(dalloc(c, t.codes, sizeof(unsigned) * M));
+    TRY(dalloc(c, t.vals, sizeof(double) * M));
+    hipStream_t st = c->stream;
+    if (M > 0) {
+        hipLaunchKernelGGL(k_expand, dim3(grid1(n, 128)), dim3(128), 0, st, rkeys.as<unsigned long long>(), n, mode,
+                           (int)per, ekeys.as<unsigned long long>(), epay.as<unsigned long long>());
+    }
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid1(cap, 256)), dim3(256), 0, st, t.keys.as<unsigned long long>(),
+                       (long long)cap, SCQ_EMPTY_KEY);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid1(cap, 256)), dim3(256), 0, st, cnt.as<unsigned>(), (long long)cap, 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid1(cap, 256)), dim3(256), 0, st, cur.as<unsigned>(), (long long)cap, 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(32), 0, st, total.as<unsigned>(), 1LL, 0u);
+    if (M > 0) {
+        hipLaunchKernelGGL(k_insert, dim3(grid1(M, 256)), dim3(256), 0, st, ekeys.as<unsigned long long>(), M,
+                           t.keys.as<unsigned long long>(), cap - 1, cnt.as<unsigned>(), slot_of.as<unsigned>());
+    }
+    hipLaunchKernelGGL(k_assign, dim3(grid1(cap, 256)), dim3(256), 0, st, cnt.as<unsigned>(), (long long)cap,
+                       off.as<unsigned>(), total.as<unsigned>());
+    if (M > 0) {
+        hipLaunchKernelGGL(k_scatter, dim3(grid1(M, 256)), dim3(256), 0, st, slot_of.as<unsigned>(),
+                           epay.as<unsigned long long>(), M, off.as<unsigned>(), cur.as<unsigned>(),
+                           tmp.as<unsigned long long>());
+    }
+    hipLaunchKernelGGL(k_finish, dim3(grid1(cap, 256)), dim3(256), 0, st, cnt.as<unsigned>(), off.as<unsigned>(),
+                       (long long)cap, tmp.as<unsigned long long>(), c->refcoef.as<double>(), t.offcnt.as<uint2>(),
+                       t.codes.as<unsigned>(), t.vals.as<double>());
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(st));
+    return SCQMC_OK;
+}
+
+scqmc_status scqmc_set_reference(scqmc_ctx *c, int64_t n_det, const uint64_t *dets, const double *coeff) {
+    if (!c) return SCQMC_E_INVALID_ARG;
+    if (!c->has_ints) FAIL(c, SCQMC_E_STATE, "set_integrals first");
+    if (n_det <= 0 || !dets || !coeff) FAIL(c, SCQMC_E_INVALID_ARG, "empty reference");
+    if (n_det > (1LL << 40)) FAIL(c, SCQMC_E_UNSUPPORTED, "reference too large");
+    if (!all_finite(coeff, n_det)) FAIL(c, SCQMC_E_NUMERIC, "non-finite reference coefficient");
+    std::vector<unsigned long long> keys(n_det);
+    bool any = false;
+    for (long long i = 0; i < n_det; i++) {
+        unsigned virt;
+        std::string why;
+        if (!compact_host(c, dets + i * 2 * c->words, keys[i], virt, why))
+            FAIL(c, SCQMC_E_INVALID_ARG, "reference determinant " + std::to_string(i) + ": " + why);
+        if (virt != (SCQ_NOVIRT | (SCQ_NOVIRT << 16)))
+            FAIL(c, SCQMC_E_INVALID_ARG, "reference determinant " + std::to_string(i) + " has a virtual electron");
+        any |= coeff[i] != 0.0;
+    }
+    if (!any) FAIL(c, SCQMC_E_INVALID_ARG, "all reference coefficients are zero");
+    std::vector<unsigned long long> sk(keys);
+    std::sort(sk.begin(), sk.end());
+    if (std::adjacent_find(sk.begin(), sk.end()) != sk.end()) FAIL(c, SCQMC_E_INVALID_ARG, "duplicate reference determinant");
+    HIPCHK(c, hipSetDevice(c->device));
+    DBuf rk;
+    TRY(dalloc(c, rk, sizeof(unsigned long long) * n_det));
+    TRY(dalloc(c, c->refcoef, sizeof(double) * n_det));
+    HIPCHK(c, hipMemcpyAsync(rk.p, keys.data(), sizeof(unsigned long long) * n_det, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->refcoef.p, coeff, sizeof(double) * n_det, hipMemcpyHostToDevice, c->stream));
+    TRY(build_table(c, 0, rk, n_det, c->ref));
+    TRY(build_table(c, 1, rk, n_det, c->ytab));
+    TRY(build_table(c, 2, rk, n_det, c->xtab));
+    c->n_ref = n_det;
+    c->has_ref = true;
+    c->has_walkers = false;
+    return SCQMC_OK;
+}
+
+scqmc_status scqmc_set_sc_coeffs(scqmc_ctx *c, double c0, const double *c_cls, int64_t n) {
+    if (!c) return SCQMC_E_INVALID_ARG;
+    if (!c->has_ref) FAIL(c, SCQMC_E_STATE, "set_reference first");
+    if (n != c->ncls - 1 || (n > 0 && !c_cls))
+        FAIL(c, SCQMC_E_INVALID_ARG, "expected " + std::to_string(c->ncls - 1) + " class coefficients");
+    if (!std::isfinite(c0) || !all_finite(c_cls, n)) FAIL(c, SCQMC_E_NUMERIC, "non-finite coefficient");
+    c->ccls_h.assign(c->ncls, 0.0);
+    c->ccls_h[0] = c0;
+    for (long long i = 0; i < n; i++) c->ccls_h[i + 1] = c_cls[i];
+    HIPCHK(c, hipSetDevice(c->device));
+    TRY(dalloc(c, c->ccls, sizeof(double) * c->ncls));
+    HIPCHK(c, hipMemcpyAsync(c->ccls.p, c->ccls_h.data(), sizeof(double) * c->ncls, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->has_coef = true;
+    c->has_walkers = false;
+    return SCQMC_OK;
+}
+
+scqmc_status scqmc_set_dyall(scqmc_ctx *c, const double *eps_virt, double e0_ref) {
+    if (!c) return SCQMC_E_INVALID_ARG;
+    if (!c->has_coef) FAIL(c, SCQMC_E_STATE, "set_sc_coeffs first");
+    if (!eps_virt && c->V > 0) FAIL(c, SCQMC_E_INVALID_ARG, "null eps_virt");
+    if (!std::isfinite(e0_ref) || !all_finite(eps_virt, c->V)) FAIL(c, SCQMC_E_NUMERIC, "non-finite Dyall input");
+    c->eps_h.assign(eps_virt, eps_virt + c->V);
+    HIPCHK(c, hipSetDevice(c->device));
+    TRY(dalloc(c, c->eps, sizeof(double) * std::max(c->V, 1)));
+    HIPCHK(c, hipMemcpyAsync(c->eps.p, c->eps_h.data(), sizeof(double) * c->V, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->e0_ref = e0_ref;
+    c->has_dyall = true;
+    return SCQMC_OK;
+}
+
+scqmc_status scqmc_set_options(scqmc_ctx *c, const scqmc_options *o) {
+    if (!c || !o) return SCQMC_E_INVALID_ARG;
+    if (!c->has_space) FAIL(c, SCQMC_E_STATE, "set_space first");
+    if (!std::isfinite(o->eps_screen) || o->eps_screen < 0) FAIL(c, SCQMC_E_INVALID_ARG, "eps_screen must be >= 0");
+    if (o->mode != 0 && o->mode != 1) FAIL(c, SCQMC_E_INVALID_ARG, "mode must be 0 or 1");
+    if (o->precision != 0) FAIL(c, SCQMC_E_UNSUPPORTED, "only the FP64 form is implemented");
+    if (o->burn_in < 0 || o->block_len < 0) FAIL(c, SCQMC_E_INVALID_ARG, "negative burn_in / block_len");
+    c->opt = *o;
+    return SCQMC_OK;
+}
+
+static size_t kernel_lds(const scqmc_ctx *c) { return WPB * wave_lds_bytes(lists_per_group(c)); }
+
+static scqmc_status ready_for_walkers(scqmc_ctx *c) {
+    if (!c->has_coef) FAIL(c, SCQMC_E_STATE, "set_space / integrals / reference / sc_coeffs first");
+    if (c->opt.mode == 1 && !c->has_dyall) FAIL(c, SCQMC_E_STATE, "mode 1 needs set_dyall");
+    return SCQMC_OK;
+}
+
+scqmc_status scqmc_init_walkers(scqmc_ctx *c, int64_t W, const uint64_t *dets, uint64_t seed) {
+    if (!c) return SCQMC_E_INVALID_ARG;
+    TRY(ready_for_walkers(c));
+    if (W <= 0 || W >= (1LL << 31) || !dets) FAIL(c, SCQMC_E_INVALID_ARG, "n_walkers must be in [1, 2^31)");
+    std::vector<unsigned long long> keys(W);
+    std::vector<unsigned> virts(W);
+    for (long long i = 0; i < W; i++) {
+        std::string why;
+        if (!compact_host(c, dets + i * 2 * c->words, keys[i], virts[i], why))
+            FAIL(c, SCQMC_E_INVALID_ARG, "walker " + std::to_string(i) + ": " + why);
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    TRY(dalloc(c, c->wkey, sizeof(unsigned long long) * W));
+    TRY(dalloc(c, c->wvirt, sizeof(unsigned) * W));
+    TRY(dalloc(c, c->wpsi, sizeof(double) * W));
+    TRY(dalloc(c, c->wsum, sizeof(double) * 3 * W));
+    TRY(dalloc(c, c->cacc, sizeof(unsigned long long) * 8 * c->ncls));
+    TRY(dalloc(c, c->bad, sizeof(unsigned long long)));
+    HIPCHK(c, hipMemcpyAsync(c->wkey.p, keys.data(), sizeof(unsigned long long) * W, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->wvirt.p, virts.data(), sizeof(unsigned) * W, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->wsum.p, 0, sizeof(double) * 3 * W, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->cacc.p, 0, sizeof(unsigned long long) * 8 * c->ncls, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->bad.p, 0, sizeof(unsigned long long), c->stream));
+    c->seed = seed;
+    DevProblem P = dev_problem(c);
+    hipLaunchKernelGGL(k_psi, dim3(grid1(W, 64)), dim3(64), 0, c->stream, P, c->wkey.as<unsigned long long>(),
+                       c->wvirt.as<unsigned>(), (long long)W, c->wpsi.as<double>());
+    HIPCHK(c, hipGetLastError());
+    std::vector<double> psi(W);
+    HIPCHK(c, hipMemcpyAsync(psi.data(), c->wpsi.p, sizeof(double) * W, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (long long i = 0; i < W; i++) {
+        if (!std::isfinite(psi[i])) FAIL(c, SCQMC_E_NUMERIC, "walker " + std::to_string(i) + ": non-finite psi");
+        if (psi[i] == 0.0) FAIL(c, SCQMC_E_INVALID_ARG, "walker " + std::to_string(i) + " has psi = 0");
+    }
+    c->W = W;
+    c->step = 0;
+    c->has_walkers = true;
+    return SCQMC_OK;
+}
+
+scqmc_status scqmc_sample(scqmc_ctx *c, int64_t n_steps) {
+    if (!c) return SCQMC_E_INVALID_ARG;
+    if (!c->has_walkers) FAIL(c, SCQMC_E_STATE, "init_walkers first");
+    if (c->opt.mode == 1 && !c->has_dyall) FAIL(c, SCQMC_E_STATE, "mode 1 needs set_dyall");
+    if (n_steps < 0) FAIL(c, SCQMC_E_INVALID_ARG, "negative n_steps");
+    if (c->step + n_steps >= (1LL << 31)) FAIL(c, SCQMC_E_UNSUPPORTED, "step counter limit (2^31) reached");
+    HIPCHK(c, hipSetDevice(c->device));
+    DevProblem P = dev_problem(c);
+    WalkerArrays S;
+    S.key = c->wkey.as<unsigned long long>();
+    S.virt = c->wvirt.as<unsigned>();
+    S.psi = c->wpsi.as<double>();
+    S.wsum = c->wsum.as<double>();
+    S.cacc = c->cacc.as<unsigned long long>();
+    S.bad = c->bad.as<unsigned long long>();
+    int NL = lists_per_group(c);
+    size_t lds = kernel_lds(c);
+    long long blk = c->opt.block_len > 0 ? c->opt.block_len : 1;
+    for (long long done = 0; done < n_steps; done += blk) {
+        int ns = (int)std::min(blk, n_steps - done);
+        hipLaunchKernelGGL(k_sample, dim3(grid1(c->W, WPB)), dim3(64 * WPB), lds, c->stream, P, S, c->W,
+                           c->step + done, ns, (long long)c->opt.burn_in, NL);
+        HIPCHK(c, hipGetLastError());
+    }
+    c->step += n_steps;
+    return SCQMC_OK;
+}
+
+scqmc_status scqmc_synchronize(scqmc_ctx *c) {
+    if (!c) return SCQMC_E_INVALID_ARG;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SCQMC_OK;
+}
+
+static scqmc_status download_sums(scqmc_ctx *c, std::vector<double> &ws, std::vector<double> &cs) {
+    ws.resize(3 * c->W);
+    std::vector<unsigned long long> acc(8 * c->ncls);
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipMemcpyAsync(ws.data(), c->wsum.p, sizeof(double) * 3 * c->W, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(acc.data(), c->cacc.p, sizeof(unsigned long long) * 8 * c->ncls, hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    cs.resize(4 * c->ncls);
+    for (long long i = 0; i < 4 * c->ncls; i++) {
+        unsigned long long lo = acc[2 * i];
+        long long hi = (long long)acc[2 * i + 1];
+        cs[i] = (double)hi + std::ldexp((double)lo, -64);
+    }
+    return SCQMC_OK;
+}
+
+scqmc_status scqmc_read_estimates(scqmc_ctx *c, scqmc_estimates *out) {
+    if (!c || !out) return SCQMC_E_INVALID_ARG;
+    if (!c->has_walkers) FAIL(c, SCQMC_E_STATE, "init_walkers first");
+    std::vector<double> ws, cs;
+    TRY(download_sums(c, ws, cs));
+    long long W = c->W;
+    // delete-one jackknife over groups of consecutive walkers
+    long long G = std::min<long long>(W, 256);
+    std::vector<double> gt(G, 0.0), gte(G, 0.0), gt0(G, 0.0);
+    for (long long w = 0; w < W; w++) {
+        long long g = w * G / W;
+        gt[g] += ws[w];
+        gte[g] += ws[W + w];
+        gt0[g] += ws[2 * W + w];
+    }
+    double St = 0, Ste = 0, St0 = 0;
+    for (long long g = 0; g < G; g++) { St += gt[g]; Ste += gte[g]; St0 += gt0[g]; }
+    std::memset(out, 0, sizeof(*out));
+    out->n_walkers = W;
+    out->n_steps_accumulated = std::max<long long>(0, c->step - c->opt.burn_in);
+    if (St > 0) {
+        out->e_var = Ste / St;
+        out->a0_sq = St0 / St;
+        double me = 0, ma = 0;
+        std::vector<double> je(G), ja(G);
+        for (long long g = 0; g < G; g++) {
+            double d = St - gt[g];
+            je[g] = d > 0 ? (Ste - gte[g]) / d : out->e_var;
+            ja[g] = d > 0 ? (St0 - gt0[g]) / d : out->a0_sq;
+            me += je[g];
+            ma += ja[g];
+        }
+        me /= G;
+        ma /= G;
+        double ve = 0, va = 0;
+        for (long long g = 0; g < G; g++) { ve += (je[g] - me) * (je[g] - me); va += (ja[g] - ma) * (ja[g] - ma); }
+        out->e_var_err = G > 1 ? std::sqrt((G - 1.0) / G * ve) : NAN;
+        out->a0_sq_err = G > 1 ? std::sqrt((G - 1.0) / G * va) : NAN;
+    } else {
+        out->e_var = out->e_var_err = out->a0_sq = out->a0_sq_err = NAN;
+    }
+    out->e_ref = c->has_dyall ? c->e0_ref : 0.0;
+    out->davidson = c->has_dyall ? (1.0 - out->a0_sq) * (out->e_var - c->e0_ref) : NAN;
+    out->e2 = NAN;
+    out->e2_err = NAN;
+    if (c->opt.mode == 1 && c->has_dyall) {
+        long long n = c->ncls;
+        double n0 = cs[2 * n + 0];
+        if (n0 > 0) {
+            double e2 = 0;
+            for (long long l = 1; l < n; l++) {
+                double nl = cs[2 * n + l];
+                if (nl <= 0) continue;
+                double el = cs[3 * n + l] / nl;
+                e2 += (nl / n0) / (c->e0_ref - el);
+            }
+            out->e2 = e2;
+        }
+    }
+    return SCQMC_OK;
+}
+
+scqmc_status scqmc_read_class_sums(scqmc_ctx *c, double *n_l, double *d_l, double *t_l, double *te_l, int64_t n) {
+    if (!c) return SCQMC_E_INVALID_ARG;
+    if (!c->has_walkers) FAIL(c, SCQMC_E_STATE, "init_walkers first");
+    if (n != c->ncls) FAIL(c, SCQMC_E_INVALID_ARG, "n must equal n_classes");
+    std::vector<double> ws, cs;
+    TRY(download_sums(c, ws, cs));
+    for (long long l = 0; l < n; l++) {
+        if (t_l) t_l[l] = cs[l];
+        if (te_l) te_l[l] = cs[n + l];
+        if (n_l) n_l[l] = cs[2 * n + l];
+        if (d_l) d_l[l] = cs[3 * n + l];
+    }
+    return SCQMC_OK;
+}
+
+scqmc_status scqmc_read_walker_sums(scqmc_ctx *c, double *sum_t, double *sum_te, double *sum_t0, int64_t n) {
+    if (!c) return SCQMC_E_INVALID_ARG;
+    if (!c->has_walkers) FAIL(c, SCQMC_E_STATE, "init_walkers first");
+    if (n != c->W) FAIL(c, SCQMC_E_INVALID_ARG, "n must equal n_walkers");
+    std::vector<double> ws, cs;
+    TRY(download_sums(c, ws, cs));
+    for (long long w = 0; w < n; w++) {
+        if (sum_t) sum_t[w] = ws[w];
+        if (sum_te) sum_te[w] = ws[n + w];
+        if (sum_t0) sum_t0[w] = ws[2 * n + w];
+    }
+    return SCQMC_OK;
+}
+
+scqmc_status scqmc_read_walkers(scqmc_ctx *c, uint64_t *dets, double *psi, int64_t n) {
+    if (!c) return SCQMC_E_INVALID_ARG;
+    if (!c->has_walkers) FAIL(c, SCQMC_E_STATE, "init_walkers first");
+    if (n != c->W) FAIL(c, SCQMC_E_INVALID_ARG, "n must equal n_walkers");
+    std::vector<unsigned long long> keys(n);
+    std::vector<unsigned> virts(n);
+    std::vector<double> ps(n);
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipMemcpyAsync(keys.data(), c->wkey.p, sizeof(unsigned long long) * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(virts.data(), c->wvirt.p, sizeof(unsigned) * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(ps.data(), c->wpsi.p, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (long long w = 0; w < n; w++) {
+        if (dets) expand_host(c, keys[w], virts[w], dets + w * 2 * c->words);
+        if (psi) psi[w] = ps[w];
+    }
+    return SCQMC_OK;
+}
+
+scqmc_status scqmc_read_counters(scqmc_ctx *c, int64_t *steps, int64_t *bad_steps) {
+    if (!c) return SCQMC_E_INVALID_ARG;
+    if (!c->has_walkers) FAIL(c, SCQMC_E_STATE, "init_walkers first");
+    unsigned long long b = 0;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipMemcpyAsync(&b, c->bad.p, sizeof(b), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (steps) *steps = c->step;
+    if (bad_steps) *bad_steps = (int64_t)b;
+    return SCQMC_OK;
+}
+
+scqmc_status scqmc_eval_snapshot(scqmc_ctx *c, int64_t n, const uint64_t *d_dets, double *d_eloc, double *d_psi,
+                                 double *d_gamma, double *d_eloc_dyall, int32_t *d_class) {
+    if (!c) return SCQMC_E_INVALID_ARG;
+    TRY(ready_for_walkers(c));
+    if (n < 0 || (n > 0 && !d_dets)) FAIL(c, SCQMC_E_INVALID_ARG, "bad snapshot arguments");
+    if (n == 0) return SCQMC_OK;
+    HIPCHK(c, hipSetDevice(c->device));
+    if (c->skey.n < sizeof(unsigned long long) * n) {
+        TRY(dalloc(c, c->skey, sizeof(unsigned long long) * n));
+        TRY(dalloc(c, c->svirt, sizeof(unsigned) * n));
+        TRY(dalloc(c, c->svalid, sizeof(int) * n));
+    }
+    hipLaunchKernelGGL(k_compact, dim3(grid1(n, 128)), dim3(128), 0, c->stream, (const unsigned long long *)d_dets,
+                       (long long)n, c->words, c->N, c->C, c->A, c->na, c->nb, c->skey.as<unsigned long long>(),
+                       c->svirt.as<unsigned>(), c->svalid.as<int>());
+    DevProblem P = dev_problem(c);
+    int NL = lists_per_group(c);
+    hipLaunchKernelGGL(k_eval, dim3(grid1(n, WPB)), dim3(64 * WPB), kernel_lds(c), c->stream, P,
+                       c->skey.as<unsigned long long>(), c->svirt.as<unsigned>(), c->svalid.as<int>(), (long long)n,
+                       NL, d_eloc, d_psi, d_gamma, (c->opt.mode == 1 && c->has_dyall) ? d_eloc_dyall : nullptr,
+                       (int *)d_class);
+    HIPCHK(c, hipGetLastError());
+    if (d_eloc_dyall && !(c->opt.mode == 1 && c->has_dyall)) {
+        std::vector<double> nanv(n, NAN);
+        HIPCHK(c, hipMemcpyAsync(d_eloc_dyall, nanv.data(), sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return SCQMC_OK;
+}
+
+scqmc_status scqmc_debug_neighbors(scqmc_ctx *c, const uint64_t *det, int64_t cap, uint64_t *out_dets,
+                                   int8_t *out_phase, double *out_hnm, double *out_psi, int64_t *out_count) {
+    if (!c) return SCQMC_E_INVALID_ARG;
+    TRY(ready_for_walkers(c));
+    if (!det || cap < 0 || !out_count) FAIL(c, SCQMC_E_INVALID_ARG, "bad arguments");
+    unsigned long long key;
+    unsigned virt;
+    std::string why;
+    if (!compact_host(c, det, key, virt, why)) FAIL(c, SCQMC_E_INVALID_ARG, "determinant: " + why);
+    HIPCHK(c, hipSetDevice(c->device));
+    long long m = std::max<long long>(cap, 1);
+    DBuf k, v, ph, h, p, cnt;
+    TRY(dalloc(c, k, sizeof(unsigned long long) * m));
+    TRY(dalloc(c, v, sizeof(unsigned) * m));
+    TRY(dalloc(c, ph, sizeof(signed char) * m));
+    TRY(dalloc(c, h, sizeof(double) * m));
+    TRY(dalloc(c, p, sizeof(double) * m));
+    TRY(dalloc(c, cnt, sizeof(unsigned long long)));
+    HIPCHK(c, hipMemsetAsync(cnt.p, 0, sizeof(unsigned long long), c->stream));
+    DevProblem P = dev_problem(c);
+    int NL = lists_per_group(c);
+    hipLaunchKernelGGL(k_neighbors, dim3(1), dim3(64), wave_lds_bytes(NL), c->stream, P, key, virt, NL, (long long)cap,
+                       k.as<unsigned long long>(), v.as<unsigned>(), ph.as<signed char>(), h.as<double>(),
+                       p.as<double>(), cnt.as<unsigned long long>());
+    HIPCHK(c, hipGetLastError());
+    unsigned long long total = 0;
+    HIPCHK(c, hipMemcpyAsync(&total, cnt.p, sizeof(total), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    long long nw = std::min<long long>((long long)total, cap);
+    std::vector<unsigned long long> kk(nw);
+    std::vector<unsigned> vv(nw);
+    if (nw > 0) {
+        HIPCHK(c, hipMemcpy(kk.data(), k.p, sizeof(unsigned long long) * nw, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(vv.data(), v.p, sizeof(unsigned) * nw, hipMemcpyDeviceToHost));
+        if (out_phase) HIPCHK(c, hipMemcpy(out_phase, ph.p, nw, hipMemcpyDeviceToHost));
+        if (out_hnm) HIPCHK(c, hipMemcpy(out_hnm, h.p, sizeof(double) * nw, hipMemcpyDeviceToHost));
+        if (out_psi) HIPCHK(c, hipMemcpy(out_psi, p.p, sizeof(double) * nw, hipMemcpyDeviceToHost));
+        if (out_dets)
+            for (long long i = 0; i < nw; i++) expand_host(c, kk[i], vv[i], out_dets + i * 2 * c->words);
+    }
+    *out_count = (int64_t)total;
+    return SCQMC_OK;
+}
+
+// checkpoint layout: header of 12 int64, then key[W] u64, virt[W] u32 (padded to 8),
+// psi[W], wsum[3W], cacc[8 ncls] u64, bad u64
+static const int64_t kMagic = 0x31435153514d4353LL;
+
+static int64_t state_bytes(const scqmc_ctx *c) {
+    int64_t W = c->W;
+    return 12 * 8 + 8 * W + ((4 * W + 7) / 8) * 8 + 8 * W + 24 * W + 64 * c->ncls + 8;
+}
+
+scqmc_status scqmc_save_state(scqmc_ctx *c, void *buf, int64_t cap, int64_t *used) {
+    if (!c || !used) return SCQMC_E_INVALID_ARG;
+    if (!c->has_walkers) FAIL(c, SCQMC_E_STATE, "init_walkers first");
+    int64_t need = state_bytes(c);
+    *used = need;
+    if (!buf || cap < need) FAIL(c, SCQMC_E_INVALID_ARG, "buffer too small");
+    char *b = (char *)buf;
+    std::memset(b, 0, need);
+    int64_t hdr[12] = {kMagic, 1, c->W, c->ncls, c->N, c->C, c->A, c->na, c->nb, c->step, (int64_t)c->seed, c->n_ref};
+    std::memcpy(b, hdr, sizeof(hdr));
+    int64_t W = c->W, o = 96;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(b + o, c->wkey.p, 8 * W, hipMemcpyDeviceToHost)); o += 8 * W;
+    HIPCHK(c, hipMemcpy(b + o, c->wvirt.p, 4 * W, hipMemcpyDeviceToHost)); o += ((4 * W + 7) / 8) * 8;
+    HIPCHK(c, hipMemcpy(b + o, c->wpsi.p, 8 * W, hipMemcpyDeviceToHost)); o += 8 * W;
+    HIPCHK(c, hipMemcpy(b + o, c->wsum.p, 24 * W, hipMemcpyDeviceToHost)); o += 24 * W;
+    HIPCHK(c, hipMemcpy(b + o, c->cacc.p, 64 * c->ncls, hipMemcpyDeviceToHost)); o += 64 * c->ncls;
+    HIPCHK(c, hipMemcpy(b + o, c->bad.p, 8, hipMemcpyDeviceToHost));
+    return SCQMC_OK;
+}
+
+scqmc_status scqmc_load_state(scqmc_ctx *c, const void *buf, int64_t len) {
+    if (!c || !buf) return SCQMC_E_INVALID_ARG;
+    TRY(ready_for_walkers(c));
+    if (len < 96) FAIL(c, SCQMC_E_INVALID_ARG, "state buffer too short");
+    int64_t hdr[12];
+    std::memcpy(hdr, buf, sizeof(hdr));
+    if (hdr[0] != kMagic || hdr[1] != 1) FAIL(c, SCQMC_E_INVALID_ARG, "not a checkpoint");
+    if (hdr[3] != c->ncls || hdr[4] != c->N || hdr[5] != c->C || hdr[6] != c->A || hdr[7] != c->na ||
+        hdr[8] != c->nb || hdr[11] != c->n_ref)
+        FAIL(c, SCQMC_E_INVALID_ARG, "checkpoint from a different problem");
+    int64_t W = hdr[2];
+    if (W <= 0 || W >= (1LL << 31)) FAIL(c, SCQMC_E_INVALID_ARG, "bad walker count in checkpoint");
+    c->W = W;
+    if (len < state_bytes(c)) FAIL(c, SCQMC_E_INVALID_ARG, "state buffer too short");
+    const char *b = (const char *)buf;
+    HIPCHK(c, hipSetDevice(c->device));
+    TRY(dalloc(c, c->wkey, 8 * W));
+    TRY(dalloc(c, c->wvirt, 4 * W));
+    TRY(dalloc(c, c->wpsi, 8 * W));
+    TRY(dalloc(c, c->wsum, 24 * W));
+    TRY(dalloc(c, c->cacc, 64 * c->ncls));
+    TRY(dalloc(c, c->bad, 8));
+    int64_t o = 96;
+    HIPCHK(c, hipMemcpy(c->wkey.p, b + o, 8 * W, hipMemcpyHostToDevice)); o += 8 * W;
+    HIPCHK(c, hipMemcpy(c->wvirt.p, b + o, 4 * W, hipMemcpyHostToDevice)); o += ((4 * W + 7) / 8) * 8;
+    HIPCHK(c, hipMemcpy(c->wpsi.p, b + o, 8 * W, hipMemcpyHostToDevice)); o += 8 * W;
+    HIPCHK(c, hipMemcpy(c->wsum.p, b + o, 24 * W, hipMemcpyHostToDevice)); o += 24 * W;
+    HIPCHK(c, hipMemcpy(c->cacc.p, b + o, 64 * c->ncls, hipMemcpyHostToDevice)); o += 64 * c->ncls;
+    HIPCHK(c, hipMemcpy(c->bad.p, b + o, 8, hipMemcpyHostToDevice));
+    c->step = hdr[9];
+    c->seed = (unsigned long long)hdr[10];
+    c->has_walkers = true;
+    return SCQMC_OK;
+}
+
+}  // extern "C"

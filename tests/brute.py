@@ -232,6 +232,13 @@ def eloc_tol(eloc, sabs, kappa, n_nbr, floor=1e-10):
     return np.maximum(floor, b)
 
 
+def gamma_rtol(kappa, n_nbr, floor=1e-12):
+    """Relative tolerance of Gamma = sum_m |psi(m)| / |psi(n)|: 1e-12, widened
+    by the condition number kappa of psi(n) (its relative rounding is
+    ~2^-53 kappa) times the number of summed terms' square root."""
+    return np.maximum(floor, 16.0 * 2.0 ** -53 * np.asarray(kappa) * np.sqrt(np.asarray(n_nbr) + 1.0))
+
+
 def count_neighbors(A, V, a_occ, v_occ):
     """|M(n)| for a walker with a_occ = (alpha, beta) active electrons and
     v_occ = (alpha, beta) virtual electrons, A active and V virtual orbitals

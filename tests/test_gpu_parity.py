@@ -1,0 +1,171 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bar: neighbour sets and phases bit-exact; H_nm to 1e-12; psi to 1e-12
+relative to the largest overlap; local energies to 1e-10 Eh widened only by
+the rounding bound of the sum for near-node walkers (brute.eloc_tol);
+rates to 1e-12 relative; classes exact.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import brute
+import oracle as O
+from helpers import TINY, cfg1_problem, det_key, sample_by_class, tiny_problem
+from paper_1909_06935_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def engine_for(prob, mode=1, eps_screen=0.0, burn_in=0, block_len=0):
+    from paper_1909_06935_amd.scqmc import Engine
+    return Engine.from_problem(prob, mode=mode, eps_screen=eps_screen, burn_in=burn_in, block_len=block_len)
+
+
+def compare_eval(gpu, ref, n_nbr, label):
+    g = {k: v.cpu().numpy() for k, v in gpu.items()}
+    ok = ref["psi"] != 0
+    scale = max(1e-300, np.abs(ref["psi"]).max())
+    assert np.all(np.abs(g["psi"] - ref["psi"]) <= 1e-12 * scale), label
+    assert np.array_equal(g["cls"].astype(np.int64), ref["cls"]), label
+    tol = brute.eloc_tol(ref["eloc"], ref["sabs"], ref["kappa"], n_nbr)
+    d = np.abs(g["eloc"] - ref["eloc"])
+    bad = ok & ~(d <= tol)
+    assert not bad.any(), (label, np.nonzero(bad)[0][:5], d[bad][:5], tol[bad][:5])
+    assert np.all(np.isnan(g["eloc"][~ok]))
+    rel = np.abs(g["gamma"][ok] - ref["gamma"][ok]) / ref["gamma"][ok]
+    rtol = brute.gamma_rtol(ref["kappa"][ok], np.asarray(n_nbr)[ok] if np.ndim(n_nbr) else n_nbr)
+    assert np.all(rel <= rtol), (label, rel.max())
+    okd = ok & ~np.isnan(ref["eloc_d"])
+    dd = np.abs(g["eloc_d"] - ref["eloc_d"])
+    told = brute.eloc_tol(ref["eloc_d"], ref["sabs"], ref["kappa"], n_nbr)
+    assert np.all(dd[okd] <= told[okd]), (label, dd[okd].max())
+
+
+def compare_neighbors(eng, orc, det, label):
+    g = eng.debug_neighbors(det)
+    o = orc.neighbors(det)
+    assert g["count"] == len(o["h"]), (label, g["count"], len(o["h"]))
+    gi = {det_key(d): i for i, d in enumerate(g["dets"])}
+    assert len(gi) == g["count"], label
+    scale = max(1e-300, np.abs(o["psi"]).max())
+    for j, d in enumerate(o["dets"]):
+        i = gi[det_key(d)]
+        assert int(g["phase"][i]) == int(o["phase"][j]), (label, j)
+        assert abs(g["h"][i] - o["h"][j]) <= 1e-12, (label, j, g["h"][i], o["h"][j])
+        assert abs(g["psi"][i] - o["psi"][j]) <= 1e-12 * scale, (label, j, g["psi"][i], o["psi"][j])
+
+
+@pytest.mark.parametrize("case", TINY, ids=lambda c: "c%d_a%d_v%d_%d%d" % c[:5])
+def test_tiny_eval_and_neighbors(case):
+    prob = tiny_problem(case)
+    _say("tiny", case)
+    eng = engine_for(prob, mode=1)
+    orc = O.Oracle.from_problem(prob, mode=1)
+    b = brute.allowed_space(prob.space)
+    dets = np.array([brute.int_to_det(prob.space, x) for x in b])
+    ref = orc.eval(dets)
+    nn = np.array([len(orc.neighbors(d)["h"]) for d in dets])
+    compare_eval(eng.eval_snapshot(dets), ref, nn, f"tiny {case}")
+    for i, d in enumerate(dets):
+        compare_neighbors(eng, orc, d, f"tiny {case} det {i}")
+
+
+def test_tiny_screened_neighbors():
+    prob = tiny_problem(TINY[0])
+    _say("tiny screened")
+    eng = engine_for(prob, mode=1, eps_screen=0.05)
+    orc = O.Oracle.from_problem(prob, mode=1, eps_screen=0.05)
+    dets = np.array([brute.int_to_det(prob.space, x) for x in brute.allowed_space(prob.space)])
+    ref = orc.eval(dets)
+    nn = np.array([len(orc.neighbors(d)["h"]) for d in dets])
+    compare_eval(eng.eval_snapshot(dets), ref, nn, "tiny screened")
+    for i, d in enumerate(dets):
+        compare_neighbors(eng, orc, d, f"screened det {i}")
+
+
+def test_cfg1_all_determinants():
+    prob = cfg1_problem()
+    _say("cfg1 eval")
+    eng = engine_for(prob, mode=1)
+    orc = O.Oracle.from_problem(prob, mode=1)
+    dets = np.array([brute.int_to_det(prob.space, x) for x in brute.allowed_space(prob.space)])
+    ref = orc.eval(dets)
+    nn = np.array([len(orc.neighbors(d)["h"]) for d in dets])
+    compare_eval(eng.eval_snapshot(dets), ref, nn, "cfg1")
+    for i in range(0, len(dets), 37):
+        compare_neighbors(eng, orc, dets[i], f"cfg1 det {i}")
+
+
+def test_cfg1_trajectory():
+    """Same chain on both sides: after k steps every walker sits on the same
+    determinant and the accumulated sums agree."""
+    prob = cfg1_problem()
+    _say("cfg1 trajectory")
+    W, K = 64, 30
+    w0 = wl.draw_walkers(prob.ref_dets, prob.ref_coeff, W, prob.seed_walk)
+    eng = engine_for(prob, mode=1, burn_in=5, block_len=7)
+    eng.init_walkers(w0, prob.seed_walk)
+    eng.sample(K)
+    gd, gpsi = eng.read_walkers()
+    gws = eng.read_walker_sums()
+    gcs = eng.read_class_sums()
+    steps, bad = eng.read_counters()
+    assert steps == K and bad == 0
+    orc = O.Oracle.from_problem(prob, mode=1)
+    od, opsi, ows, ocs, stuck = orc.run(w0, prob.seed_walk, K, burn_in=5)
+    assert stuck == 0
+    same = np.array([np.array_equal(gd[i], od[i]) for i in range(W)])
+    assert same.all(), np.nonzero(~same)[0]
+    assert np.allclose(gpsi, opsi, rtol=1e-11, atol=0)
+    assert np.allclose(gws, ows, rtol=1e-10, atol=1e-12)
+    assert np.allclose(gcs["t"], ocs[:, 0], rtol=1e-10, atol=1e-12)
+    assert np.allclose(gcs["te"], ocs[:, 1], rtol=1e-10, atol=1e-10)
+    assert np.allclose(gcs["n"], ocs[:, 2], rtol=1e-10, atol=1e-10)
+    assert np.allclose(gcs["d"], ocs[:, 3], rtol=1e-10, atol=1e-9)
+
+
+def test_cfg2_snapshot_and_neighbors():
+    prob = wl.make_problem("cfg2")
+    prob.eps_virt = np.linspace(1.0, 3.0, prob.space.n_virt)
+    prob.e0_ref = float(np.load(wl.reference_file("cfg2"))["e_cas"])
+    _say("cfg2 snapshot")
+    orc = O.Oracle.from_problem(prob, mode=1)
+    dets = sample_by_class(orc, prob.space, prob.ref_dets, 6, 2024)
+    eng = engine_for(prob, mode=1)
+    ref = orc.eval(dets)
+    nn = np.array([len(orc.neighbors(d)["h"]) for d in dets])
+    compare_eval(eng.eval_snapshot(dets), ref, nn, "cfg2")
+    for i in (0, len(dets) // 2, len(dets) - 1):
+        compare_neighbors(eng, orc, dets[i], f"cfg2 det {i}")
+
+
+def test_cfg3_counts_and_foi_snapshot():
+    prob = wl.make_problem("cfg3")
+    _say("cfg3 counts")
+    eng = engine_for(prob, mode=0)
+    sp = prob.space
+    g = eng.debug_neighbors(prob.ref_dets[0], cap=0)
+    assert g["count"] == brute.count_neighbors(14, 76, [7, 7], [0, 0]) == 481649
+    orc = O.Oracle.from_problem(prob, mode=0)
+    # first-order-space determinants: neighbours of a reference determinant
+    d0 = prob.ref_dets[len(prob.ref_dets) // 2]
+    gn = eng.debug_neighbors(d0)
+    rng = np.random.Generator(np.random.PCG64(7))
+    nz = np.nonzero(gn["psi"] != 0)[0]
+    pick = gn["dets"][rng.choice(nz, size=6, replace=False)]
+    _say("cfg3 snapshot")
+    ref = orc.eval(pick, nthreads=8)
+    nn = np.zeros(len(pick))
+    from helpers import virtual_count
+    for i, d in enumerate(pick):
+        oa, ob = wl.unpack_det(sp, d)
+        a_occ = [sum(sp.n_core <= p < sp.n_core + sp.n_act for p in oa), sum(sp.n_core <= p < sp.n_core + sp.n_act for p in ob)]
+        nn[i] = brute.count_neighbors(14, 76, a_occ, list(virtual_count(sp, d)))
+    compare_eval(eng.eval_snapshot(pick), ref, nn, "cfg3")
