@@ -65,6 +65,7 @@ def lib():
         L.orc_det_hamiltonian.restype = C.c_int64
         L.orc_det_hamiltonian.argtypes = [P, C.c_int64, up, C.c_int64, P, P, P]
         L.orc_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
+        L.orc_traffic.argtypes = [P, up, C.POINTER(C.c_int64)]
         L.orc_exp_draw.restype = C.c_double
         L.orc_exp_draw.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]
         _lib = L
@@ -202,6 +203,13 @@ class Oracle:
         stuck = lib().orc_run(self.h, W, dets.reshape(-1), _ptr(psi), int(seed), int(step0), int(n_steps),
                               int(burn_in), int(wid0), wsum.reshape(-1), csum.reshape(-1), int(nthreads))
         return dets, psi, wsum, csum, int(stuck)
+
+    def traffic(self, det):
+        """Distinct operands one walker-step on det reads: dict(eri, heff, ref,
+        n_nbr, terms) -- see orc_traffic in scqmc_oracle.c."""
+        out = (C.c_int64 * 5)()
+        lib().orc_traffic(self.h, self._det(det), out)
+        return dict(eri=out[0], heff=out[1], ref=out[2], n_nbr=out[3], terms=out[4])
 
     def det_hamiltonian(self, dets):
         """Sparse (COO, upper triangle) Hamiltonian over a determinant list."""

@@ -726,3 +726,145 @@ int64_t orc_det_hamiltonian(const orc_t *o, int64_t n, const uint64_t *dets, int
         }
     return nnz;
 }
+
+/* ------------------------------------------------------------------ */
+/* Algorithmic data volume of one walker-step (bench roofline figure)   */
+/* ------------------------------------------------------------------ */
+/* Counts the DISTINCT operands the local-energy sums of one walker-step
+ * read, in the frozen-core formulation: two-electron integrals over
+ * non-core orbitals (8-fold canonical index), entries of the core-folded
+ * one-body operator (canonical pair) and reference determinants whose
+ * coefficient enters a nonzero term.  Each element counts once however
+ * often it is used. */
+typedef struct { uint64_t *k; int64_t cap, n; } uset;
+static void uset_add(uset *s, uint64_t key) {
+    key += 1;  /* 0 marks a free slot */
+    if (2 * (s->n + 1) > s->cap) {
+        int64_t nc = s->cap ? 2 * s->cap : 1024;
+        uint64_t *nk = (uint64_t *)calloc((size_t)nc, sizeof(uint64_t));
+        for (int64_t i = 0; i < s->cap; i++)
+            if (s->k[i]) {
+                uint64_t h = (s->k[i] * 0x9E3779B97F4A7C15ull) >> 20;
+                int64_t j = (int64_t)(h & (uint64_t)(nc - 1));
+                while (nk[j]) j = (j + 1) & (nc - 1);
+                nk[j] = s->k[i];
+            }
+        free(s->k);
+        s->k = nk;
+        s->cap = nc;
+    }
+    uint64_t h = (key * 0x9E3779B97F4A7C15ull) >> 20;
+    int64_t j = (int64_t)(h & (uint64_t)(s->cap - 1));
+    while (s->k[j]) { if (s->k[j] == key) return; j = (j + 1) & (s->cap - 1); }
+    s->k[j] = key;
+    s->n++;
+}
+static uint64_t pair_idx(uint64_t a, uint64_t b) { return a > b ? a * (a + 1) / 2 + b : b * (b + 1) / 2 + a; }
+static void count_eri(const orc_t *o, uset *si, int P, int Q, int R, int S) {
+    if (spin(o, P) != spin(o, Q) || spin(o, R) != spin(o, S)) return;
+    uint64_t pq = pair_idx((uint64_t)(orb(o, P) - o->C), (uint64_t)(orb(o, Q) - o->C));
+    uint64_t rs = pair_idx((uint64_t)(orb(o, R) - o->C), (uint64_t)(orb(o, S) - o->C));
+    uset_add(si, pair_idx(pq, rs));
+}
+/* operands of <a|H|b> (a != b, at most doubly excited) */
+static void count_hmat(const orc_t *o, const uint64_t *a, const uint64_t *b, uset *si, uset *sh) {
+    int N2 = 2 * o->N, rem[3], add[3], nr = 0, na = 0;
+    for (int g = 0; g < N2; g++) {
+        int x = bit(o, a, g), y = bit(o, b, g);
+        if (y && !x) { if (nr < 3) rem[nr] = g; nr++; }
+        if (x && !y) { if (na < 3) add[na] = g; na++; }
+    }
+    if (nr == 1) {
+        int P = rem[0], Q = add[0];
+        uset_add(sh, pair_idx((uint64_t)(orb(o, P) - o->C), (uint64_t)(orb(o, Q) - o->C)));
+        for (int J = 0; J < N2; J++) {
+            if (!bit(o, b, J) || J == P || is_core(o, J)) continue;
+            count_eri(o, si, Q, P, J, J);
+            count_eri(o, si, Q, J, J, P);
+        }
+    } else if (nr == 2) {
+        count_eri(o, si, add[0], rem[0], add[1], rem[1]);
+        count_eri(o, si, add[0], rem[1], add[1], rem[0]);
+    }
+}
+/* out[0] distinct two-electron integrals, out[1] distinct one-body entries,
+ * out[2] distinct reference determinants, out[3] |M(n)|, out[4] nonzero
+ * overlap terms (with repetition) */
+void orc_traffic(const orc_t *o, const uint64_t *n, int64_t out[5]) {
+    nbr_list L = {0, 0, 0};
+    enumerate(o, n, &L);
+    uset si = {0, 0, 0}, sh = {0, 0, 0}, sr = {0, 0, 0};
+    int64_t terms = 0;
+    int W2 = 2 * o->W, N2 = 2 * o->N;
+    /* diagonal */
+    for (int i = 0; i < N2; i++) {
+        if (!bit(o, n, i) || is_core(o, i)) continue;
+        uset_add(&sh, pair_idx((uint64_t)(orb(o, i) - o->C), (uint64_t)(orb(o, i) - o->C)));
+        for (int j = 0; j < N2; j++) {
+            if (!bit(o, n, j) || is_core(o, j)) continue;
+            count_eri(o, &si, i, i, j, j);
+            count_eri(o, &si, i, j, j, i);
+        }
+    }
+    uint64_t d[2 * MAXW];
+    for (int64_t k = 0; k < L.n; k++) {
+        const uint64_t *m = L.v[k].det;
+        count_hmat(o, m, n, &si, &sh);
+        int nv = n_virt_el(o, m);
+        if (nv == 0) {
+            if (ref_lookup(o, m) != 0.0) {
+                /* reference index as key */
+                uint64_t key = 0;
+                for (int w = 0; w < W2; w++) key = key * 0x100000001B3ull ^ m[w];
+                uset_add(&sr, key);
+                terms++;
+            }
+            continue;
+        }
+        int vir[2], nvir = 0, occa[MAXE], nocca = 0, hol[MAXE], nhol = 0;
+        for (int g = 0; g < N2; g++) {
+            if (is_virt(o, g) && bit(o, m, g)) vir[nvir++] = g;
+            if (is_act(o, g)) { if (bit(o, m, g)) occa[nocca++] = g; else hol[nhol++] = g; }
+        }
+#define VISIT()                                                               \
+        do {                                                                  \
+            if (ref_lookup(o, d) != 0.0) {                                    \
+                uint64_t key = 0;                                             \
+                for (int w = 0; w < W2; w++) key = key * 0x100000001B3ull ^ d[w]; \
+                uset_add(&sr, key);                                           \
+                count_hmat(o, m, d, &si, &sh);                                \
+                terms++;                                                      \
+            }                                                                 \
+        } while (0)
+        if (nv == 1) {
+            int X = vir[0];
+            for (int i = 0; i < nhol; i++) {
+                int T = hol[i];
+                if (spin(o, T) != spin(o, X)) continue;
+                memcpy(d, m, sizeof(uint64_t) * W2); flip(o, d, X); flip(o, d, T);
+                VISIT();
+            }
+            for (int r = 0; r < nocca; r++)
+                for (int i = 0; i < nhol; i++)
+                    for (int j = i + 1; j < nhol; j++) {
+                        int R = occa[r], T = hol[i], S = hol[j];
+                        if (spin(o, T) + spin(o, S) != spin(o, X) + spin(o, R)) continue;
+                        memcpy(d, m, sizeof(uint64_t) * W2);
+                        flip(o, d, X); flip(o, d, R); flip(o, d, T); flip(o, d, S);
+                        VISIT();
+                    }
+        } else {
+            for (int i = 0; i < nhol; i++)
+                for (int j = i + 1; j < nhol; j++) {
+                    int T = hol[i], S = hol[j];
+                    if (spin(o, T) + spin(o, S) != spin(o, vir[0]) + spin(o, vir[1])) continue;
+                    memcpy(d, m, sizeof(uint64_t) * W2);
+                    flip(o, d, vir[0]); flip(o, d, vir[1]); flip(o, d, T); flip(o, d, S);
+                    VISIT();
+                }
+        }
+#undef VISIT
+    }
+    out[0] = si.n; out[1] = sh.n; out[2] = sr.n; out[3] = L.n; out[4] = terms;
+    free(si.k); free(sh.k); free(sr.k); free(L.v);
+}
