@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC_DIR = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libscqmc.so")
-SOURCES = ["scqmc_host.hip", "scqmc_kernels.hip", "scqmc_device.h"]
+SOURCES = ["scqmc_host.hip", "scqmc_walk.hip", "scqmc_setup.hip", "scqmc_device.h"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -20,8 +20,7 @@
 #define SCQ_NOVIRT 0xFFFFu
 
 struct DevTable {
-    const unsigned long long *keys;  // [cap], SCQ_EMPTY_KEY = free slot
-    const uint2 *offcnt;             // [cap]: (offset, count) into codes / vals
+    const ulonglong2 *slots;         // [cap]: .x key (SCQ_EMPTY_KEY = free), .y = count << 32 | offset
     const uint32_t *codes;           // entry codes (ytab: t; xtab: t<<6 | u; ref: 0)
     const double *vals;              // entry reference coefficients
     unsigned long long mask;         // cap - 1 (cap a power of two)
@@ -58,14 +57,14 @@ __device__ __forceinline__ unsigned long long scq_hash(unsigned long long k) {
     return k;
 }
 
-// Open-addressing lookup (linear probing).  Returns the (offset, count) of
-// the key's entry list, count 0 when absent.
+// Open-addressing lookup (linear probing, one 16-byte load per probe).
+// Returns the (offset, count) of the key's entry list, count 0 when absent.
 __device__ __forceinline__ uint2 table_find(const DevTable &t, unsigned long long key) {
     unsigned long long slot = scq_hash(key) & t.mask;
     while (true) {
-        unsigned long long k = t.keys[slot];
-        if (k == key) return t.offcnt[slot];
-        if (k == SCQ_EMPTY_KEY) return make_uint2(0u, 0u);
+        ulonglong2 s = t.slots[slot];
+        if (s.x == key) return make_uint2((unsigned)s.y, (unsigned)(s.y >> 32));
+        if (s.x == SCQ_EMPTY_KEY) return make_uint2(0u, 0u);
         slot = (slot + 1) & t.mask;
     }
 }
@@ -102,10 +101,12 @@ __device__ __forceinline__ long long class_id2(int V, int s1, int s2) {
 // ---------------------------------------------------------------------------
 // determinants over non-core spin-orbitals
 // ---------------------------------------------------------------------------
+#define SCQ_NOG 0x3fffffff   // absent virtual electron (compares above every spin-orbital)
+
 struct NDet {           // occupation: active key + up to two virtual electrons (g codes, ascending)
     unsigned long long key;
     int nv;
-    int vg[2];
+    int vg[2];          // SCQ_NOG where absent; only constant indices are used (registers, no scratch)
 };
 
 __device__ __forceinline__ int g_of_active(const DevProblem &P, int c) { return (c >> 5) * P.Np + (c & 31); }
@@ -122,17 +123,22 @@ __device__ __forceinline__ int below(const DevProblem &P, const NDet &d, int g) 
     int idx = g - sg * P.Np;
     uint32_t act = (uint32_t)(d.key >> (32 * sg));
     int c = 0;
-    if (sg) {
-        c += popc32((uint32_t)d.key);
-        for (int i = 0; i < d.nv; i++) c += (d.vg[i] < P.Np);
-    }
+    if (sg) c += popc32((uint32_t)d.key) + (d.vg[0] < P.Np) + (d.vg[1] < P.Np);
     if (idx < P.A) {
         c += popc32(act & ((1u << idx) - 1u));
     } else {
-        c += popc32(act);
-        for (int i = 0; i < d.nv; i++) c += (d.vg[i] >= sg * P.Np && d.vg[i] < g);
+        int lo = sg * P.Np;
+        c += popc32(act) + (d.vg[0] >= lo && d.vg[0] < g) + (d.vg[1] >= lo && d.vg[1] < g);
     }
     return c;
+}
+
+// number of non-core occupied spin-orbitals of an active-space determinant
+// (key) below active code c, in creation order (all alpha, then beta)
+__device__ __forceinline__ int key_below(unsigned long long k, int c) {
+    int sg = c >> 5, t = c & 31;
+    unsigned mask = (1u << t) - 1u;
+    return sg ? __popc((unsigned)k) + __popc((unsigned)(k >> 32) & mask) : __popc((unsigned)k & mask);
 }
 
 // sign of <m| a+_Q a_P |b>
@@ -183,7 +189,9 @@ __device__ __forceinline__ double single_elem(const DevProblem &P, const NDet &b
         }
     }
     if (with_virt) {
-        for (int i = 0; i < b.nv; i++) {
+#pragma unroll
+        for (int i = 0; i < 2; i++) {
+            if (i >= b.nv) break;
             int gJ = b.vg[i];
             if (gJ == gP) continue;
             int j = g_idx(P, gJ), s = g_spin(P, gJ);
@@ -193,35 +201,4 @@ __device__ __forceinline__ double single_elem(const DevProblem &P, const NDet &b
         }
     }
     return v;
-}
-
-// diagonal <b|H|b> over non-core electrons plus E_core (with_virt = 0: the
-// active part only, i.e. Dyall's H_0 without the orbital-energy term)
-__device__ inline double diag_elem(const DevProblem &P, const NDet &b, bool with_virt) {
-    int gs[72];
-    int n = 0;
-    for (int s = 0; s < 2; s++) {
-        uint32_t act = (uint32_t)(b.key >> (32 * s));
-        while (act) {
-            int t = __ffs(act) - 1;
-            act &= act - 1u;
-            gs[n++] = s * P.Np + t;
-        }
-    }
-    if (with_virt)
-        for (int i = 0; i < b.nv; i++) gs[n++] = b.vg[i];
-    double v = P.e_core;
-    for (int i = 0; i < n; i++) {
-        int ii = g_idx(P, gs[i]);
-        v += P.heff[ii * P.Np + ii];
-    }
-    double two = 0.0;
-    for (int i = 0; i < n; i++)
-        for (int j = 0; j < n; j++) {
-            int ii = g_idx(P, gs[i]), jj = g_idx(P, gs[j]);
-            double J = eri4(P, ii, ii, jj, jj);
-            double K = g_spin(P, gs[i]) == g_spin(P, gs[j]) ? eri4(P, ii, jj, jj, ii) : 0.0;
-            two += J - K;
-        }
-    return v + 0.5 * two;
 }

@@ -15,7 +15,8 @@
 #include <vector>
 
 #include "../../include/scqmc.h"
-#include "scqmc_kernels.hip"
+#include "scqmc_setup.hip"
+#include "scqmc_walk.hip"
 
 namespace {
 
@@ -32,12 +33,11 @@ struct DBuf {
 };
 
 struct TableBufs {
-    DBuf keys, offcnt, codes, vals;
-    unsigned long long cap = 0;
+    DBuf slots, codes, vals;
+    unsigned long long cap = 0, unique = 0;
     DevTable view() const {
         DevTable t;
-        t.keys = keys.as<unsigned long long>();
-        t.offcnt = offcnt.as<uint2>();
+        t.slots = slots.as<ulonglong2>();
         t.codes = codes.as<uint32_t>();
         t.vals = vals.as<double>();
         t.mask = cap ? cap - 1 : 0;
@@ -324,49 +324,67 @@ scqmc_status scqmc_set_integrals_dense(scqmc_ctx *c, const double *h1, const dou
     return SCQMC_OK;
 }
 
+// Multimap from 64-bit keys to lists of (code, coefficient), built on the
+// device: expand the reference determinants into (key, payload) pairs, count
+// distinct keys in a scratch table, insert into a table of 4x that many
+// 16-byte slots (load <= 1/4), give every key a contiguous range, scatter the
+// payloads, sort each list (deterministic content order).
 static scqmc_status build_table(scqmc_ctx *c, int mode, const DBuf &rkeys, long long n, TableBufs &t) {
     int ne = c->nea + c->neb;
     long long per = mode == 0 ? 1 : mode == 1 ? ne : (long long)ne * (ne - 1) / 2;
     long long M = n * per;
-    unsigned long long cap = 64;
-    while (cap < 2ull * (unsigned long long)std::max(M, 1LL)) cap <<= 1;
-    t.cap = cap;
-    DBuf ekeys, epay, cnt, off, cur, slot_of, tmp, total;
+    hipStream_t st = c->stream;
+    DBuf ekeys, epay, cnt, off, cur, slot_of, tmp, total, scratch, uniq;
     TRY(dalloc(c, ekeys, sizeof(unsigned long long) * M));
     TRY(dalloc(c, epay, sizeof(unsigned long long) * M));
+    TRY(dalloc(c, uniq, sizeof(unsigned)));
+    unsigned long long cap1 = 64;
+    while (cap1 < 2ull * (unsigned long long)std::max(M, 1LL)) cap1 <<= 1;
+    TRY(dalloc(c, scratch, sizeof(unsigned long long) * cap1));
+    if (M > 0)
+        hipLaunchKernelGGL(k_expand, dim3(grid1(n, 128)), dim3(128), 0, st, rkeys.as<unsigned long long>(), n, mode,
+                           (int)per, ekeys.as<unsigned long long>(), epay.as<unsigned long long>());
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid1(cap1, 256)), dim3(256), 0, st, scratch.as<unsigned long long>(),
+                       (long long)cap1, SCQ_EMPTY_KEY);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(32), 0, st, uniq.as<unsigned>(), 1LL, 0u);
+    if (M > 0)
+        hipLaunchKernelGGL(k_insert, dim3(grid1(M, 256)), dim3(256), 0, st, ekeys.as<unsigned long long>(), M,
+                           scratch.as<unsigned long long>(), 1, cap1 - 1, (unsigned *)nullptr, (unsigned *)nullptr,
+                           uniq.as<unsigned>());
+    unsigned U = 0;
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(&U, uniq.p, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    scratch.release();
+    unsigned long long cap = 64;
+    while (cap < 4ull * U) cap <<= 1;
+    t.cap = cap;
+    t.unique = U;
     TRY(dalloc(c, cnt, sizeof(unsigned) * cap));
     TRY(dalloc(c, off, sizeof(unsigned) * cap));
     TRY(dalloc(c, cur, sizeof(unsigned) * cap));
     TRY(dalloc(c, slot_of, sizeof(unsigned) * M));
     TRY(dalloc(c, tmp, sizeof(unsigned long long) * M));
     TRY(dalloc(c, total, sizeof(unsigned)));
-    TRY(dalloc(c, t.keys, sizeof(unsigned long long) * cap));
-    TRY(dalloc(c, t.offcnt, sizeof(uint2) * cap));
+    TRY(dalloc(c, t.slots, sizeof(ulonglong2) * cap));
     TRY(dalloc(c, t.codes, sizeof(unsigned) * M));
     TRY(dalloc(c, t.vals, sizeof(double) * M));
-    hipStream_t st = c->stream;
-    if (M > 0) {
-        hipLaunchKernelGGL(k_expand, dim3(grid1(n, 128)), dim3(128), 0, st, rkeys.as<unsigned long long>(), n, mode,
-                           (int)per, ekeys.as<unsigned long long>(), epay.as<unsigned long long>());
-    }
-    hipLaunchKernelGGL(k_fill_u64, dim3(grid1(cap, 256)), dim3(256), 0, st, t.keys.as<unsigned long long>(),
-                       (long long)cap, SCQ_EMPTY_KEY);
+    hipLaunchKernelGGL(k_fill_slots, dim3(grid1(cap, 256)), dim3(256), 0, st, t.slots.as<ulonglong2>(), (long long)cap);
     hipLaunchKernelGGL(k_fill_u32, dim3(grid1(cap, 256)), dim3(256), 0, st, cnt.as<unsigned>(), (long long)cap, 0u);
     hipLaunchKernelGGL(k_fill_u32, dim3(grid1(cap, 256)), dim3(256), 0, st, cur.as<unsigned>(), (long long)cap, 0u);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(32), 0, st, total.as<unsigned>(), 1LL, 0u);
-    if (M > 0) {
+    if (M > 0)
         hipLaunchKernelGGL(k_insert, dim3(grid1(M, 256)), dim3(256), 0, st, ekeys.as<unsigned long long>(), M,
-                           t.keys.as<unsigned long long>(), cap - 1, cnt.as<unsigned>(), slot_of.as<unsigned>());
-    }
+                           (unsigned long long *)t.slots.p, 2, cap - 1, cnt.as<unsigned>(), slot_of.as<unsigned>(),
+                           (unsigned *)nullptr);
     hipLaunchKernelGGL(k_assign, dim3(grid1(cap, 256)), dim3(256), 0, st, cnt.as<unsigned>(), (long long)cap,
                        off.as<unsigned>(), total.as<unsigned>());
-    if (M > 0) {
+    if (M > 0)
         hipLaunchKernelGGL(k_scatter, dim3(grid1(M, 256)), dim3(256), 0, st, slot_of.as<unsigned>(),
                            epay.as<unsigned long long>(), M, off.as<unsigned>(), cur.as<unsigned>(),
                            tmp.as<unsigned long long>());
-    }
     hipLaunchKernelGGL(k_finish, dim3(grid1(cap, 256)), dim3(256), 0, st, cnt.as<unsigned>(), off.as<unsigned>(),
-                       (long long)cap, tmp.as<unsigned long long>(), c->refcoef.as<double>(), t.offcnt.as<uint2>(),
+                       (long long)cap, tmp.as<unsigned long long>(), c->refcoef.as<double>(), t.slots.as<ulonglong2>(),
                        t.codes.as<unsigned>(), t.vals.as<double>());
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(st));

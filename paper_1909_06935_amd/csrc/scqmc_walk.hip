@@ -1,0 +1,855 @@
+// scqmc_walk.hip -- the hot path: one continuous-time step of every walker
+// (local energy of eq:locE with the overlaps of eq:ovlp, the rates and move of
+// the rejection-free walk of "SC-MRCI(s)", the Dyall local energy of eq:nevpt).
+//
+// Layout: one wave64 per walker.  The neighbours m of walker n are grouped by
+// their active part x_m = x_n - Ra + Pa (Ra: up to two removed active
+// spin-orbitals, Pa: up to two added).  Members of a group differ only in the
+// virtual occupation l_m, i.e. the SC class.  Groups are swept in "blocks"
+// fixed by the spin kinds of Ra and Pa (none, a, b, aa, ab, bb each): inside a
+// block every group has the same number of rows (virtual sets reachable by at
+// most a double excitation) and the same overlap type, so the wave processes
+// a block without divergence:
+//   1. 64 groups at a time, one per lane: decode (Ra, Pa), form x_m and do the
+//      group's reference-table lookups once
+//        l_m empty      : phi0(x_m)                       (reference table)
+//        one virtual    : y-list of x_m, x-lists of x_m - r for each electron r
+//        two virtuals   : x-list of x_m
+//      (a y-list / x-list holds the reference determinants a determinant with
+//      one / two active electrons removed came from, with their coefficients);
+//   2. all lanes sweep the 64 x R rows: H_nm (Slater-Condon with phase) and
+//      psi(m) = c_l <m|H|phi0> summed over the group's lists, i.e. over
+//      nonzero reference terms only;
+//   3. per-group rate sums by a segmented scan in registers (fixed order).
+// The next state: first-reaction method at two levels (exponential clocks keyed
+// by (walker, step, x_m), then by (walker, step, class)) -- independent of the
+// visiting order.
+#include "scqmc_device.h"
+
+#define WAVE 64
+#define WPB 4   // walkers (waves) per 256-thread block
+
+// wave-uniform values: keep them in scalar registers
+__device__ __forceinline__ unsigned uni(unsigned v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ unsigned long long uni(unsigned long long v) {
+    return ((unsigned long long)uni((unsigned)(v >> 32)) << 32) | (unsigned long long)uni((unsigned)v);
+}
+__device__ __forceinline__ double uni(double v) {
+    return __longlong_as_double((long long)uni((unsigned long long)__double_as_longlong(v)));
+}
+
+struct GroupInfo {
+    unsigned long long xkey;
+    double phi;           // phi0(x_m) for groups without virtual electrons
+    double gam;           // sum over rows of |psi(m)|
+    signed char ra[2], pa[2];
+    int pad;
+};
+
+struct WaveLDS {
+    GroupInfo *G;          // [65]; slot 64 holds the selected group
+    uint2 *lst;            // [65 * NL]
+    unsigned char *occ;    // [2][32] active occupied codes per spin
+    unsigned char *hol;    // [2][32] active holes per spin
+    short *wg;             // [72] g codes of the walker's occupied non-core spin-orbitals (active, then virtual)
+    int NL;
+};
+
+__host__ __device__ inline size_t wave_lds_bytes(int NL) {
+    size_t b = 65 * sizeof(GroupInfo) + 65 * (size_t)NL * sizeof(uint2) + 128 + 72 * sizeof(short);
+    return (b + 15) & ~(size_t)15;
+}
+
+__device__ inline WaveLDS carve(unsigned char *base, int NL) {
+    WaveLDS L;
+    L.G = (GroupInfo *)base;
+    L.lst = (uint2 *)(base + 65 * sizeof(GroupInfo));
+    L.occ = (unsigned char *)(L.lst + 65 * NL);
+    L.hol = L.occ + 64;
+    L.wg = (short *)(L.hol + 64);
+    L.NL = NL;
+    return L;
+}
+
+struct WalkerCtx {
+    NDet n;
+    int vcode[2];   // virtual codes, ascending
+    int vs[2];      // virtual electrons per spin
+    int e[2], h[2]; // active electrons / holes per spin
+    int ne, nocc;   // active electrons, all non-core electrons
+};
+
+struct Block {
+    int rk, pk;          // spin kinds of Ra and Pa: 0 none, 1 a, 2 b, 3 aa, 4 ab, 5 bb
+    int vp[2];           // virtual electrons per spin of the block's neighbours
+    int nra, npa;
+    unsigned fam_end[4]; // cumulative rows per kept subset of the walker's virtual electrons
+    unsigned R;          // rows per group
+    long long ng, npk;   // groups, choices of Pa
+};
+
+__device__ __forceinline__ unsigned binom012(int n, int k) {
+    if (k == 0) return 1u;
+    if (n < k) return 0u;
+    if (k == 1) return (unsigned)n;
+    return (unsigned)(n * (n - 1) / 2);
+}
+
+// pair index k -> (i < j), k = j(j-1)/2 + i
+__device__ __forceinline__ void pair_decode(unsigned k, int &i, int &j) {
+    int jj = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)k)) * 0.5f);
+    while (jj * (jj - 1) / 2 > (int)k) jj--;
+    while ((jj + 1) * jj / 2 <= (int)k) jj++;
+    j = jj;
+    i = (int)k - jj * (jj - 1) / 2;
+}
+
+__device__ __forceinline__ int kind_a(int k) { return (k == 1 || k == 4) ? 1 : (k == 3 ? 2 : 0); }
+__device__ __forceinline__ int kind_b(int k) { return (k == 2 || k == 4) ? 1 : (k == 5 ? 2 : 0); }
+__device__ __forceinline__ long long kind_count(int k, int a, int b) {
+    switch (k) {
+        case 0: return 1;
+        case 1: return a;
+        case 2: return b;
+        case 3: return (long long)a * (a - 1) / 2;
+        case 4: return (long long)a * b;
+        default: return (long long)b * (b - 1) / 2;
+    }
+}
+// index within a kind -> up to two active codes (ascending)
+__device__ __forceinline__ int kind_decode(int k, unsigned idx, const unsigned char *la, const unsigned char *lb,
+                                           int nb, int &o0, int &o1) {
+    o0 = o1 = -1;
+    int i, j;
+    switch (k) {
+        case 0: return 0;
+        case 1: o0 = la[idx]; return 1;
+        case 2: o0 = lb[idx]; return 1;
+        case 3: pair_decode(idx, i, j); o0 = la[i]; o1 = la[j]; return 2;
+        case 4: o0 = la[idx / nb]; o1 = lb[idx % nb]; return 2;
+        default: pair_decode(idx, i, j); o0 = lb[i]; o1 = lb[j]; return 2;
+    }
+}
+
+// k-th virtual orbital of spin sg not occupied by the walker -> virtual code
+__device__ __forceinline__ int avail_virtual(const DevProblem &P, const WalkerCtx &W, int sg, int k) {
+    int a = k, lo = sg * P.V;
+    // the walker's virtual codes are ascending (absent = -1, never in range)
+    int c0 = W.vcode[0] - lo, c1 = W.vcode[1] - lo;
+    if (W.vcode[0] >= lo && c0 < P.V && c0 <= a) a++;
+    if (W.vcode[1] >= lo && c1 < P.V && c1 <= a) a++;
+    return lo + a;
+}
+
+__device__ __forceinline__ void sort2(int *v, int n) {
+    if (n == 2 && v[0] > v[1]) { int t = v[0]; v[0] = v[1]; v[1] = t; }
+}
+
+__device__ bool block_setup(const DevProblem &P, const WalkerCtx &W, int rk, int pk, Block &b) {
+    int r0 = kind_a(rk), r1 = kind_b(rk), p0 = kind_a(pk), p1 = kind_b(pk);
+    b.rk = rk;
+    b.pk = pk;
+    b.vp[0] = W.vs[0] + r0 - p0;
+    b.vp[1] = W.vs[1] + r1 - p1;
+    if (b.vp[0] < 0 || b.vp[1] < 0 || b.vp[0] + b.vp[1] > 2) return false;
+    b.nra = r0 + r1;
+    b.npa = p0 + p1;
+    long long nrk = kind_count(rk, W.e[0], W.e[1]);
+    b.npk = kind_count(pk, W.h[0], W.h[1]);
+    b.ng = nrk * b.npk;
+    if (b.ng == 0) return false;
+    unsigned tot = 0;
+#pragma unroll
+    for (int km = 0; km < 4; km++) {
+        unsigned rows = 0;
+        if (km < (1 << W.n.nv)) {
+            int k0 = 0, k1 = 0, nk = 0;
+#pragma unroll
+            for (int i = 0; i < 2; i++)
+                if (i < W.n.nv && ((km >> i) & 1)) { nk++; if (W.vcode[i] >= P.V) k1++; else k0++; }
+            int a0 = b.vp[0] - k0, a1 = b.vp[1] - k1;
+            int rem = b.nra + (W.n.nv - nk), add = b.npa + a0 + a1;
+            if (a0 >= 0 && a1 >= 0 && rem >= 1 && rem <= 2 && add == rem)
+                rows = binom012(P.V - W.vs[0], a0) * binom012(P.V - W.vs[1], a1);
+        }
+        tot += rows;
+        b.fam_end[km] = tot;
+    }
+    b.R = tot;
+    return tot > 0;
+}
+
+// group g of block b: decode (Ra, Pa), form x_m, do the lookups of its overlap type
+__device__ void group_setup(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, const Block &b, long long g,
+                            GroupInfo &G, uint2 *lst) {
+    unsigned ri = (unsigned)(g / b.npk), pi = (unsigned)(g - (long long)ri * b.npk);
+    int ra0, ra1, pa0, pa1;
+    kind_decode(b.rk, ri, L.occ, L.occ + 32, W.e[1], ra0, ra1);
+    kind_decode(b.pk, pi, L.hol, L.hol + 32, W.h[1], pa0, pa1);
+    unsigned long long x = W.n.key;
+    if (ra0 >= 0) x &= ~(1ull << ra0);
+    if (ra1 >= 0) x &= ~(1ull << ra1);
+    if (pa0 >= 0) x |= 1ull << pa0;
+    if (pa1 >= 0) x |= 1ull << pa1;
+    G.xkey = x;
+    G.ra[0] = (signed char)ra0; G.ra[1] = (signed char)ra1;
+    G.pa[0] = (signed char)pa0; G.pa[1] = (signed char)pa1;
+    G.gam = 0.0;
+    G.phi = 0.0;
+    int vp = b.vp[0] + b.vp[1];
+    if (vp == 0) {
+        uint2 oc = table_find(P.ref, x);
+        G.phi = oc.y ? P.ref.vals[oc.x] : 0.0;
+    } else if (vp == 2) {
+        lst[0] = table_find(P.xtab, x);
+    } else {
+        lst[0] = table_find(P.ytab, x);
+        int k = 1;
+        unsigned long long y = x;
+        while (y) {
+            int r = __ffsll((long long)y) - 1;
+            y &= y - 1ull;
+            lst[k++] = table_find(P.xtab, x & ~(1ull << r));
+        }
+    }
+}
+
+// h_eff[Q][P] + sum_{J in occ, J != P} [(QP|JJ) - delta_spin (QJ|JP)] over the
+// walker's occupied list (first `n` entries of wg), independent loads
+__device__ __forceinline__ double single_elem_w(const DevProblem &P, const WaveLDS &L, int n, int gP, int gQ) {
+    int p = g_idx(P, gP), q = g_idx(P, gQ), sp = g_spin(P, gP);
+    double v = P.heff[q * P.Np + p];
+#pragma unroll 4
+    for (int i = 0; i < n; i++) {
+        int gJ = L.wg[i];
+        int j = g_idx(P, gJ);
+        double J = eri4(P, j, j, p, q);
+        double K = eri4(P, p, j, j, q);
+        double t = J - (g_spin(P, gJ) == sp ? K : 0.0);
+        v += (gJ == gP) ? 0.0 : t;
+    }
+    return v;
+}
+
+// h_eff[s][t] + sum_{j in y} [(st|jj) - delta (sj|jt)] with y = x_n - Ra + Pa,
+// iterated as the walker's active electrons minus Ra plus Pa
+__device__ __forceinline__ double fock_y(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L,
+                                         const GroupInfo &G, int gT, int gS) {
+    int t = g_idx(P, gT), s = g_idx(P, gS), st = g_spin(P, gT);
+    int r0 = G.ra[0] >= 0 ? g_of_active(P, G.ra[0]) : -1, r1 = G.ra[1] >= 0 ? g_of_active(P, G.ra[1]) : -1;
+    double v = P.heff[s * P.Np + t];
+#pragma unroll 4
+    for (int i = 0; i < W.ne; i++) {
+        int gJ = L.wg[i];
+        int j = g_idx(P, gJ);
+        double J = eri4(P, j, j, t, s);
+        double K = eri4(P, t, j, j, s);
+        double x = J - (g_spin(P, gJ) == st ? K : 0.0);
+        v += (gJ == r0 || gJ == r1) ? 0.0 : x;
+    }
+    for (int i = 0; i < 2; i++) {
+        if (G.pa[i] < 0) continue;
+        int gJ = g_of_active(P, G.pa[i]);
+        int j = g_idx(P, gJ);
+        double J = eri4(P, j, j, t, s);
+        double K = (g_spin(P, gJ) == st) ? eri4(P, t, j, j, s) : 0.0;
+        v += J - K;
+    }
+    return v;
+}
+
+// <m|H|phi0> for m = y + virtual s.  Table coefficients carry the part of each
+// Slater-Condon phase that depends on the reference determinant (the
+// annihilation of its removed electrons); the rest depends on spins and on the
+// electron r only.  `fock` gives the single-excitation element.
+template <class ListFn, class FockFn>
+__device__ double phi1(const DevProblem &P, unsigned long long y, int s, ListFn lists, FockFn fock) {
+    int sg = s >= P.V;
+    int gs = g_of_virtual(P, s);
+    int bs = sg ? P.nea + P.neb : P.nea;   // electrons below s in any active-space determinant
+    double acc1 = 0.0;
+    uint2 oc = lists(0);
+    for (unsigned k = 0; k < oc.y; k++) {
+        int t = (int)P.ytab.codes[oc.x + k];
+        acc1 += P.ytab.vals[oc.x + k] * fock(g_of_active(P, t), gs);
+    }
+    double acc = ((bs - 1) & 1) ? -acc1 : acc1;
+    unsigned long long yy = y;
+    int li = 1;
+    while (yy) {
+        int r = __ffsll((long long)yy) - 1;
+        yy &= yy - 1ull;
+        uint2 ox = lists(li++);
+        if (!ox.y) continue;
+        int gr = g_of_active(P, r);
+        int Q1 = gs < gr ? gs : gr, Q2 = gs < gr ? gr : gs;
+        unsigned long long yr = y & ~(1ull << r);
+        for (unsigned k = 0; k < ox.y; k++) {
+            unsigned code = P.xtab.codes[ox.x + k];
+            int t = (int)(code >> 6), u = (int)(code & 63u);
+            if (t == r || u == r) continue;
+            double w = P.xtab.vals[ox.x + k];
+            int P1 = g_of_active(P, t), P2 = g_of_active(P, u);
+            int br = key_below(yr | (1ull << t) | (1ull << u), r);
+            int b1 = Q1 == gs ? bs : br, b2 = Q2 == gs ? bs : br;
+            int e = b2 - (P1 < Q2) - (P2 < Q2) + b1 - (P1 < Q1) - (P2 < Q1);
+            double el = double_elem(P, P1, P2, Q1, Q2);
+            acc += (e & 1) ? -w * el : w * el;
+        }
+    }
+    return acc;
+}
+
+// <m|H|phi0> for m = x + virtuals s1 < s2, from the x-list of x (signed coefficients)
+__device__ double phi2(const DevProblem &P, int s1, int s2, uint2 ox) {
+    int sg1 = s1 >= P.V, sg2 = s2 >= P.V;
+    int a1 = P.A + s1 - sg1 * P.V, a2 = P.A + s2 - sg2 * P.V;
+    double acc = 0.0;
+    if (sg1 != sg2) {
+        // alpha-beta pair: only (s1 t|s2 u) survives; spin part of the phase (-1)^(n_beta + 1)
+        for (unsigned k = 0; k < ox.y; k++) {
+            unsigned code = P.xtab.codes[ox.x + k];
+            int t = (int)((code >> 6) & 31u), u = (int)(code & 31u);
+            acc += P.xtab.vals[ox.x + k] * eri4(P, a1, t, a2, u);
+        }
+        return ((P.neb + 1) & 1) ? -acc : acc;
+    }
+    for (unsigned k = 0; k < ox.y; k++) {
+        unsigned code = P.xtab.codes[ox.x + k];
+        int t = (int)((code >> 6) & 31u), u = (int)(code & 31u);
+        acc += P.xtab.vals[ox.x + k] * (eri4(P, a1, t, a2, u) - eri4(P, a1, u, a2, t));
+    }
+    return acc;
+}
+
+// psi of one determinant with its own lookups (one lane; initialisation / snapshots)
+__device__ double psi_direct(const DevProblem &P, unsigned long long key, unsigned virt) {
+    int vcode[2] = {(int)(virt & 0xFFFFu), (int)(virt >> 16)};
+    int nv = (vcode[0] != (int)SCQ_NOVIRT) + (vcode[1] != (int)SCQ_NOVIRT);
+    if (nv == 0) {
+        uint2 oc = table_find(P.ref, key);
+        return oc.y ? P.ccls[0] * P.ref.vals[oc.x] : 0.0;
+    }
+    if (nv == 1) {
+        double phi = phi1(
+            P, key, vcode[0],
+            [&](int k) -> uint2 {
+                if (k == 0) return table_find(P.ytab, key);
+                unsigned long long y = key;
+                for (int i = 1; i < k; i++) y &= y - 1ull;
+                int r = __ffsll((long long)y) - 1;
+                return table_find(P.xtab, key & ~(1ull << r));
+            },
+            [&](int gT, int gS) -> double {
+                NDet d;
+                d.nv = 0;
+                d.vg[0] = d.vg[1] = SCQ_NOG;
+                d.key = key | (1ull << ((gT >= P.Np ? 32 : 0) + g_idx(P, gT)));
+                return single_elem(P, d, gT, gS, false);
+            });
+        return P.ccls[class_id1(P.V, vcode[0])] * phi;
+    }
+    return P.ccls[class_id2(P.V, vcode[0], vcode[1])] * phi2(P, vcode[0], vcode[1], table_find(P.xtab, key));
+}
+
+struct RowRes {
+    double hnm, psi, hd, phase;
+    long long cls;
+    unsigned virt;
+    bool ok, same;
+};
+
+// row r of group G in block b
+template <int VP>
+__device__ __forceinline__ void row_eval(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, const Block &b,
+                                         const GroupInfo &G, const uint2 *lst, unsigned r, RowRes &o) {
+    int km = 0;
+    unsigned start = 0;
+    if (r >= b.fam_end[0]) { km = 1; start = b.fam_end[0]; }
+    if (r >= b.fam_end[1]) { km = 2; start = b.fam_end[1]; }
+    if (r >= b.fam_end[2]) { km = 3; start = b.fam_end[2]; }
+    r -= start;
+    // kept (kc*) and removed (rm*) virtual electrons of the walker
+    int kc0 = -1, kc1 = -1, nk = 0, k0 = 0, k1 = 0, rm0 = -1, rm1 = -1, nrmv = 0;
+#pragma unroll
+    for (int i = 0; i < 2; i++) {
+        if (i >= W.n.nv) break;
+        int c = W.vcode[i];
+        if ((km >> i) & 1) {
+            if (nk == 0) kc0 = c; else kc1 = c;
+            nk++;
+            if (c >= P.V) k1++; else k0++;
+        } else {
+            if (nrmv == 0) rm0 = c; else rm1 = c;
+            nrmv++;
+        }
+    }
+    // added virtual electrons
+    int ad0 = -1, ad1 = -1, nad = 0;
+    if (VP > 0) {
+        int a0 = b.vp[0] - k0, a1 = b.vp[1] - k1;
+        unsigned c1 = binom012(P.V - W.vs[1], a1);
+        unsigned i0 = r / c1, i1 = r - i0 * c1;
+        if (a0 == 1) { ad0 = avail_virtual(P, W, 0, (int)i0); nad = 1; }
+        else if (a0 == 2) { int i, j; pair_decode(i0, i, j); ad0 = avail_virtual(P, W, 0, i); ad1 = avail_virtual(P, W, 0, j); nad = 2; }
+        if (a1 == 1) { int v = avail_virtual(P, W, 1, (int)i1); if (nad == 0) ad0 = v; else ad1 = v; nad++; }
+        else if (a1 == 2) { int i, j; pair_decode(i1, i, j); ad0 = avail_virtual(P, W, 1, i); ad1 = avail_virtual(P, W, 1, j); nad = 2; }
+    }
+    // virtual set of m (ascending)
+    int Lp0 = -1, Lp1 = -1;
+    if (VP == 1) {
+        Lp0 = nk ? kc0 : ad0;
+    } else if (VP == 2) {
+        int x0 = nk > 0 ? kc0 : ad0;
+        int x1 = nk > 1 ? kc1 : (nk == 1 ? ad0 : ad1);
+        Lp0 = x0 < x1 ? x0 : x1;
+        Lp1 = x0 < x1 ? x1 : x0;
+    }
+    o.cls = VP == 0 ? 0 : (VP == 1 ? class_id1(P.V, Lp0) : class_id2(P.V, Lp0, Lp1));
+    o.virt = (VP > 0 ? (unsigned)Lp0 : SCQ_NOVIRT) | ((VP > 1 ? (unsigned)Lp1 : SCQ_NOVIRT) << 16);
+    o.same = (nad == 0 && nk == W.n.nv);
+    // outer excitation n -> m: removed P*, added Q* (ascending spin-orbital order)
+    int Pr0 = -1, Pr1 = -1, nP = 0, Qa0 = -1, Qa1 = -1, nQ = 0;
+    if (G.ra[0] >= 0) { Pr0 = g_of_active(P, G.ra[0]); nP = 1; }
+    if (G.ra[1] >= 0) { Pr1 = g_of_active(P, G.ra[1]); nP = 2; }
+    if (nrmv > 0) { int v = g_of_virtual(P, rm0); if (nP == 0) Pr0 = v; else Pr1 = v; nP++; }
+    if (nrmv > 1) { Pr1 = g_of_virtual(P, rm1); nP = 2; }
+    if (G.pa[0] >= 0) { Qa0 = g_of_active(P, G.pa[0]); nQ = 1; }
+    if (G.pa[1] >= 0) { Qa1 = g_of_active(P, G.pa[1]); nQ = 2; }
+    if (nad > 0) { int v = g_of_virtual(P, ad0); if (nQ == 0) Qa0 = v; else Qa1 = v; nQ++; }
+    if (nad > 1) { Qa1 = g_of_virtual(P, ad1); nQ = 2; }
+    if (nP == 2 && Pr0 > Pr1) { int t = Pr0; Pr0 = Pr1; Pr1 = t; }
+    if (nQ == 2 && Qa0 > Qa1) { int t = Qa0; Qa0 = Qa1; Qa1 = t; }
+    o.hd = 0.0;
+    o.ok = true;
+    if (nP == 1) {
+        double ph = phase_single(P, W.n, Pr0, Qa0);
+        o.phase = ph;
+        o.hnm = ph * single_elem_w(P, L, W.nocc, Pr0, Qa0);
+        if (o.same && P.mode == 1) o.hd = ph * single_elem_w(P, L, W.ne, Pr0, Qa0);
+    } else {
+        double ph = phase_double(P, W.n, Pr0, Pr1, Qa0, Qa1);
+        o.phase = ph;
+        o.hnm = ph * double_elem(P, Pr0, Pr1, Qa0, Qa1);
+        o.hd = o.hnm;
+        if (P.eps_screen > 0.0 && !(fabs(o.hnm) > P.eps_screen)) { o.ok = false; o.psi = 0.0; return; }
+    }
+    double phi;
+    if (VP == 0) {
+        phi = G.phi;
+    } else if (VP == 1) {
+        phi = phi1(P, G.xkey, Lp0, [&](int k) -> uint2 { return lst[k]; },
+                   [&](int gT, int gS) -> double { return fock_y(P, W, L, G, gT, gS); });
+    } else {
+        phi = phi2(P, Lp0, Lp1, lst[0]);
+    }
+    o.psi = P.ccls[o.cls] * phi;
+}
+
+// out-of-line row evaluation for the cold paths (selected group, debug listing)
+__device__ __forceinline__ void row_eval_any(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, const Block &b,
+                                          const GroupInfo &G, const uint2 *lst, unsigned r, RowRes &o) {
+    int vp = b.vp[0] + b.vp[1];
+    if (vp == 0) row_eval<0>(P, W, L, b, G, lst, r, o);
+    else if (vp == 1) row_eval<1>(P, W, L, b, G, lst, r, o);
+    else row_eval<2>(P, W, L, b, G, lst, r, o);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+    return v;
+}
+
+__device__ inline void walker_setup(const DevProblem &P, const WaveLDS &L, int lane, unsigned long long key,
+                                    unsigned virt, WalkerCtx &W) {
+    key = uni(key);
+    virt = uni(virt);
+    W.n.key = key;
+    unsigned v0 = virt & 0xFFFFu, v1 = virt >> 16;   // ascending; v1 present only if v0 is
+    bool h0 = v0 != SCQ_NOVIRT, h1 = v1 != SCQ_NOVIRT;
+    W.n.nv = (int)h0 + (int)h1;
+    W.vcode[0] = h0 ? (int)v0 : -1;
+    W.vcode[1] = h1 ? (int)v1 : -1;
+    W.n.vg[0] = h0 ? g_of_virtual(P, (int)v0) : SCQ_NOG;
+    W.n.vg[1] = h1 ? g_of_virtual(P, (int)v1) : SCQ_NOG;
+    W.vs[0] = (h0 && v0 < (unsigned)P.V) + (h1 && v1 < (unsigned)P.V);
+    W.vs[1] = W.n.nv - W.vs[0];
+    uint32_t am = (P.A >= 32) ? 0xFFFFFFFFu : ((1u << P.A) - 1u);
+    for (int s = 0; s < 2; s++) {
+        uint32_t occ = (uint32_t)(key >> (32 * s)) & am;
+        uint32_t hol = ~(uint32_t)(key >> (32 * s)) & am;
+        W.e[s] = popc32(occ);
+        W.h[s] = popc32(hol);
+        if (lane < 32) {
+            uint32_t below = lane ? ((1u << lane) - 1u) : 0u;
+            if ((occ >> lane) & 1u) L.occ[32 * s + popc32(occ & below)] = (unsigned char)(32 * s + lane);
+            if ((hol >> lane) & 1u) L.hol[32 * s + popc32(hol & below)] = (unsigned char)(32 * s + lane);
+        }
+    }
+    W.ne = W.e[0] + W.e[1];
+    W.nocc = W.ne + W.n.nv;
+    __syncwarp();
+    if (lane < W.e[0]) L.wg[lane] = (short)g_of_active(P, L.occ[lane]);
+    else if (lane < W.ne) L.wg[lane] = (short)g_of_active(P, L.occ[32 + lane - W.e[0]]);
+    else if (lane == W.ne && W.n.nv > 0) L.wg[lane] = (short)W.n.vg[0];
+    else if (lane == W.ne + 1 && W.n.nv > 1) L.wg[lane] = (short)W.n.vg[1];
+    __syncwarp();
+}
+
+// <n|H|n> (with_virt) or <n|H_0|n> (active part only), summed over lanes in a fixed tree
+__device__ inline double wave_diag(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, int lane, bool with_virt) {
+    int n = with_virt ? W.nocc : W.ne;
+    double v = 0.0;
+    if (lane < n) {
+        int gi = L.wg[lane];
+        int ii = g_idx(P, gi), si = g_spin(P, gi);
+        double two = 0.0;
+        for (int j = 0; j < n; j++) {
+            int gj = L.wg[j];
+            int jj = g_idx(P, gj);
+            double J = eri4(P, ii, ii, jj, jj);
+            double K = (g_spin(P, gj) == si) ? eri4(P, ii, jj, jj, ii) : 0.0;
+            two += J - K;
+        }
+        v = P.heff[ii * P.Np + ii] + 0.5 * two;
+    }
+    return P.e_core + wave_sum(v);
+}
+
+struct EvalOut {
+    double eloc, elocd, gamma, psi_new;
+    unsigned long long key_new;
+    unsigned virt_new;
+    bool moved;
+};
+
+struct Acc {
+    double E, D, G;                   // sum H psi, sum H_D psi, sum |psi|
+    double best;                      // first-reaction clock of the best group so far
+    unsigned long long bestkey;
+    int bestblk;                      // rk * 6 + pk
+    long long bestg;
+};
+
+// sweep one block: groups 64 at a time, rows over all lanes
+template <bool MOVE>
+__device__ void sweep_block(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, int lane, const Block &b,
+                            uint32_t wid, uint32_t step, bool dy, Acc &a) {
+    GroupInfo &mg = L.G[lane];
+    uint2 *mlst = L.lst + lane * L.NL;
+    float invR = 1.0f / (float)b.R;
+    for (long long gb = 0; gb < b.ng; gb += WAVE) {
+        long long g = gb + lane;
+        unsigned ngc = (unsigned)min((long long)WAVE, b.ng - gb);
+        if (g < b.ng) group_setup(P, W, L, b, g, mg, mlst);
+        __syncwarp();
+        unsigned T = ngc * b.R;
+        for (unsigned fb = 0; fb < T; fb += WAVE) {
+            unsigned f = fb + (unsigned)lane;
+            int gi = WAVE;
+            double v = 0.0;
+            if (f < T) {
+                unsigned q = (unsigned)((float)f * invR);
+                if (q * b.R > f) q--;
+                if ((q + 1) * b.R <= f) q++;
+                gi = (int)q;
+                RowRes o;
+                row_eval_any(P, W, L, b, L.G[gi], L.lst + gi * L.NL, f - q * b.R, o);
+                if (o.ok) {
+                    a.E += o.hnm * o.psi;
+                    v = fabs(o.psi);
+                    a.G += v;
+                    if (dy && o.same) a.D += o.hd * o.psi;
+                }
+            }
+            if (b.R == 1) {
+                if (gi < WAVE) L.G[gi].gam += v;
+            } else {
+#pragma unroll
+                for (int d = 1; d < WAVE; d <<= 1) {
+                    double ov = __shfl_up(v, d);
+                    int og = __shfl_up(gi, d);
+                    if (lane >= d && og == gi) v += ov;
+                }
+                int ng = __shfl_down(gi, 1);
+                bool last = (lane == WAVE - 1) || (ng != gi);
+                if (last && gi < WAVE) L.G[gi].gam += v;
+            }
+            __syncwarp();
+        }
+        if (MOVE && g < b.ng && mg.gam > 0.0) {
+            double tau = exp_draw(P.seed, wid, step, 0u, (uint32_t)mg.xkey, (uint32_t)(mg.xkey >> 32)) / mg.gam;
+            if (tau < a.best || (tau == a.best && mg.xkey < a.bestkey)) {
+                a.best = tau;
+                a.bestkey = mg.xkey;
+                a.bestblk = b.rk * 6 + b.pk;
+                a.bestg = g;
+            }
+        }
+        __syncwarp();
+    }
+}
+
+template <bool MOVE>
+__device__ void walker_eval(const DevProblem &P, const WaveLDS &L, int lane, unsigned long long key, unsigned virt,
+                            double psin, uint32_t wid, uint32_t step, EvalOut &out) {
+    WalkerCtx W;
+    walker_setup(P, L, lane, key, virt, W);
+    double hnn = wave_diag(P, W, L, lane, true);
+    bool dy = (P.mode == 1 && W.n.nv > 0);
+    double hdnn = 0.0;
+    if (dy) {
+        hdnn = wave_diag(P, W, L, lane, false);
+#pragma unroll
+        for (int i = 0; i < 2; i++) {
+            if (i >= W.n.nv) break;
+            int s = W.vcode[i];
+            hdnn += P.eps[s >= P.V ? s - P.V : s];
+        }
+    }
+    Acc a;
+    a.E = a.D = a.G = 0.0;
+    a.best = INFINITY;
+    a.bestkey = ~0ull;
+    a.bestblk = -1;
+    a.bestg = -1;
+    for (int rk = 0; rk < 6; rk++)
+        for (int pk = 0; pk < 6; pk++) {
+            Block b;
+            if (!block_setup(P, W, rk, pk, b)) continue;
+            sweep_block<MOVE>(P, W, L, lane, b, wid, step, dy, a);
+        }
+    double E = wave_sum(a.E), G = wave_sum(a.G);
+    double D = dy ? wave_sum(a.D) : 0.0;
+    out.eloc = hnn + E / psin;
+    out.elocd = dy ? hdnn + D / psin : NAN;
+    out.gamma = G / fabs(psin);
+    out.moved = false;
+    if (!MOVE) return;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        double ob = __shfl_xor(a.best, d);
+        unsigned long long okk = __shfl_xor(a.bestkey, d);
+        int obk = __shfl_xor(a.bestblk, d);
+        long long og = __shfl_xor(a.bestg, d);
+        if (ob < a.best || (ob == a.best && okk < a.bestkey)) { a.best = ob; a.bestkey = okk; a.bestblk = obk; a.bestg = og; }
+    }
+    if (a.bestblk < 0) return;
+    Block b;
+    block_setup(P, W, a.bestblk / 6, a.bestblk % 6, b);
+    GroupInfo &sg = L.G[WAVE];
+    uint2 *slst = L.lst + WAVE * L.NL;
+    if (lane == 0) group_setup(P, W, L, b, a.bestg, sg, slst);
+    __syncwarp();
+    double b2 = INFINITY;
+    long long bcls = 0x7fffffffffffffffLL;
+    double bpsi = 0.0;
+    unsigned bvirt = 0;
+    for (unsigned r = lane; r < b.R; r += WAVE) {
+        RowRes o;
+        row_eval_any(P, W, L, b, sg, slst, r, o);
+        if (!o.ok || o.psi == 0.0) continue;
+        double tau = exp_draw(P.seed, wid, step, 1u, (uint32_t)o.cls, 0u) / fabs(o.psi);
+        if (tau < b2 || (tau == b2 && o.cls < bcls)) { b2 = tau; bcls = o.cls; bpsi = o.psi; bvirt = o.virt; }
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        double ob = __shfl_xor(b2, d);
+        long long oc = __shfl_xor(bcls, d);
+        double op = __shfl_xor(bpsi, d);
+        unsigned ov = __shfl_xor(bvirt, d);
+        if (ob < b2 || (ob == b2 && oc < bcls)) { b2 = ob; bcls = oc; bpsi = op; bvirt = ov; }
+    }
+    __syncwarp();
+    if (b2 == INFINITY) return;
+    out.moved = true;
+    out.psi_new = bpsi;
+    out.key_new = sg.xkey;
+    out.virt_new = bvirt;
+}
+
+// ---------------------------------------------------------------------------
+// fixed-point (2^-64 resolution, 128-bit two's complement) accumulation:
+// integer atomics make the per-class sums independent of arrival order
+// ---------------------------------------------------------------------------
+__device__ inline void to_fixed(double x, unsigned long long &lo, unsigned long long &hi) {
+    lo = 0; hi = 0;
+    if (x == 0.0 || !isfinite(x)) return;
+    int e;
+    double m = frexp(fabs(x), &e);
+    unsigned long long M = (unsigned long long)ldexp(m, 53);
+    int sh = e - 53 + 64;
+    unsigned long long l, h;
+    if (sh >= 64 + 10) { l = ~0ull; h = 0x7fffffffffffffffull; }
+    else if (sh >= 64) { l = 0; h = M << (sh - 64); }
+    else if (sh > 0) { l = M << sh; h = M >> (64 - sh); }
+    else if (sh == 0) { l = M; h = 0; }
+    else {
+        int r = -sh;
+        h = 0;
+        l = r >= 64 ? 0ull : ((M + (1ull << (r - 1))) >> r);
+    }
+    if (x < 0) { l = ~l + 1ull; h = ~h + (l == 0 ? 1ull : 0ull); }
+    lo = l; hi = h;
+}
+__device__ inline void fx_add(unsigned long long *slot, double x) {
+    unsigned long long lo, hi;
+    to_fixed(x, lo, hi);
+    if (!lo && !hi) return;
+    unsigned long long old = atomicAdd(slot, lo);
+    unsigned long long carry = (old + lo < old) ? 1ull : 0ull;
+    atomicAdd(slot + 1, hi + carry);
+}
+
+struct WalkerArrays {
+    unsigned long long *key;
+    unsigned *virt;
+    double *psi;
+    double *wsum;                 // [3][W]
+    unsigned long long *cacc;     // [4][ncls][2]
+    unsigned long long *bad;      // [1]
+};
+
+__device__ __forceinline__ long long class_of_virt(const DevProblem &P, unsigned virt) {
+    unsigned v0 = virt & 0xFFFFu, v1 = virt >> 16;
+    if (v0 == SCQ_NOVIRT) return 0;
+    if (v1 == SCQ_NOVIRT) return class_id1(P.V, (int)v0);
+    return class_id2(P.V, (int)v0, (int)v1);
+}
+
+__global__ __launch_bounds__(256) void k_sample(DevProblem P, WalkerArrays S, long long W, long long step0, int nsteps,
+                                                long long burn_in, int NL) {
+    extern __shared__ unsigned char smem[];
+    int wave = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    long long w = (long long)blockIdx.x * WPB + wave;
+    if (w >= W) return;
+    WaveLDS L = carve(smem + wave * wave_lds_bytes(NL), NL);
+    unsigned long long key = S.key[w];
+    unsigned virt = S.virt[w];
+    double psi = S.psi[w];
+    double st = S.wsum[w], ste = S.wsum[W + w], st0 = S.wsum[2 * W + w];
+    long long nbad = 0;
+    for (int k = 0; k < nsteps; k++) {
+        long long step = step0 + k;
+        EvalOut o;
+        key = uni(key);
+        virt = uni(virt);
+        psi = uni(psi);
+        walker_eval<true>(P, L, lane, key, virt, psi, (uint32_t)w, (uint32_t)step, o);
+        bool good = o.moved && isfinite(o.eloc) && o.gamma > 0.0 && isfinite(o.gamma);
+        if (!good) { nbad++; continue; }
+        if (step >= burn_in) {
+            double t = 1.0 / o.gamma;
+            long long cls = class_of_virt(P, virt);
+            st += t;
+            ste += t * o.eloc;
+            if (cls == 0) st0 += t;
+            if (lane < 4) {
+                double c = P.ccls[cls];
+                double q = lane == 0 ? t : lane == 1 ? t * o.eloc : lane == 2 ? t / (c * c)
+                                                                  : ((P.mode == 1 && cls != 0) ? t * o.elocd / (c * c) : 0.0);
+                fx_add(S.cacc + ((long long)lane * P.ncls + cls) * 2, q);
+            }
+        }
+        key = o.key_new;
+        virt = o.virt_new;
+        psi = o.psi_new;
+    }
+    if (lane == 0) {
+        S.key[w] = key;
+        S.virt[w] = virt;
+        S.psi[w] = psi;
+        S.wsum[w] = st;
+        S.wsum[W + w] = ste;
+        S.wsum[2 * W + w] = st0;
+        if (nbad) atomicAdd(S.bad, (unsigned long long)nbad);
+    }
+}
+
+// local energies without moving (parity / snapshots)
+__global__ __launch_bounds__(256) void k_eval(DevProblem P, const unsigned long long *keys, const unsigned *virts,
+                                              const int *valid, long long n, int NL, double *eloc, double *psi_out,
+                                              double *gamma, double *elocd, int *cls_out) {
+    extern __shared__ unsigned char smem[];
+    int wave = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    long long i = (long long)blockIdx.x * WPB + wave;
+    if (i >= n) return;
+    WaveLDS L = carve(smem + wave * wave_lds_bytes(NL), NL);
+    unsigned long long key = keys[i];
+    unsigned virt = virts[i];
+    int nv = ((virt & 0xFFFFu) != SCQ_NOVIRT) + ((virt >> 16) != SCQ_NOVIRT);
+    double ps = 0.0;
+    if (lane == 0 && valid[i]) ps = psi_direct(P, key, virt);
+    ps = __shfl(ps, 0);
+    EvalOut o;
+    if (ps != 0.0) {
+        walker_eval<false>(P, L, lane, key, virt, ps, (uint32_t)i, 0u, o);
+    } else {
+        o.eloc = o.elocd = o.gamma = NAN;
+    }
+    if (lane == 0) {
+        if (eloc) eloc[i] = o.eloc;
+        if (psi_out) psi_out[i] = ps;
+        if (gamma) gamma[i] = o.gamma;
+        if (elocd) elocd[i] = (P.mode == 1 && nv > 0) ? o.elocd : NAN;
+        if (cls_out) cls_out[i] = valid[i] ? (int)class_of_virt(P, virt) : -1;
+    }
+}
+
+// psi of walkers (initialisation)
+__global__ void k_psi(DevProblem P, const unsigned long long *keys, const unsigned *virts, long long n, double *psi) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    psi[i] = psi_direct(P, keys[i], virts[i]);
+}
+
+// neighbour list of one walker (debug): one wave, groups and rows one lane at a time
+template <int VP>
+__device__ void list_block(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, int lane, const Block &b,
+                           long long cap, unsigned long long *okey, unsigned *ovirt, signed char *ophase, double *ohnm,
+                           double *opsi, unsigned long long *count) {
+    GroupInfo &mg = L.G[lane];
+    uint2 *mlst = L.lst + lane * L.NL;
+    for (long long gb = 0; gb < b.ng; gb += WAVE) {
+        long long g = gb + lane;
+        if (g < b.ng) {
+            group_setup(P, W, L, b, g, mg, mlst);
+            for (unsigned r = 0; r < b.R; r++) {
+                RowRes o;
+                row_eval_any(P, W, L, b, mg, mlst, r, o);
+                if (!o.ok) continue;
+                unsigned long long pos = atomicAdd(count, 1ull);
+                if ((long long)pos < cap) {
+                    okey[pos] = mg.xkey;
+                    ovirt[pos] = o.virt;
+                    ophase[pos] = (signed char)(o.phase > 0 ? 1 : -1);
+                    ohnm[pos] = o.hnm;
+                    opsi[pos] = o.psi;
+                }
+            }
+        }
+        __syncwarp();
+    }
+}
+
+__global__ __launch_bounds__(64) void k_neighbors(DevProblem P, unsigned long long key, unsigned virt, int NL,
+                                                  long long cap, unsigned long long *okey, unsigned *ovirt,
+                                                  signed char *ophase, double *ohnm, double *opsi,
+                                                  unsigned long long *count) {
+    extern __shared__ unsigned char smem[];
+    int lane = threadIdx.x & 63;
+    WaveLDS L = carve(smem, NL);
+    WalkerCtx W;
+    walker_setup(P, L, lane, key, virt, W);
+    for (int rk = 0; rk < 6; rk++)
+        for (int pk = 0; pk < 6; pk++) {
+            Block b;
+            if (!block_setup(P, W, rk, pk, b)) continue;
+            int vp = b.vp[0] + b.vp[1];
+            if (vp == 0) list_block<0>(P, W, L, lane, b, cap, okey, ovirt, ophase, ohnm, opsi, count);
+            else if (vp == 1) list_block<1>(P, W, L, lane, b, cap, okey, ovirt, ophase, ohnm, opsi, count);
+            else list_block<2>(P, W, L, lane, b, cap, okey, ovirt, ophase, ohnm, opsi, count);
+        }
+}
