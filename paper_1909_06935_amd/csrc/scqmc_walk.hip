@@ -53,11 +53,12 @@ struct WaveLDS {
     unsigned char *occ;    // [2][32] active occupied codes per spin
     unsigned char *hol;    // [2][32] active holes per spin
     short *wg;             // [72] g codes of the walker's occupied non-core spin-orbitals (active, then virtual)
+    unsigned char *bw;     // [256] electrons of the walker below each non-core spin-orbital g (phases)
     int NL;
 };
 
 __host__ __device__ inline size_t wave_lds_bytes(int NL) {
-    size_t b = 65 * sizeof(GroupInfo) + 65 * (size_t)NL * sizeof(uint2) + 128 + 72 * sizeof(short);
+    size_t b = 65 * sizeof(GroupInfo) + 65 * (size_t)NL * sizeof(uint2) + 128 + 72 * sizeof(short) + 256;
     return (b + 15) & ~(size_t)15;
 }
 
@@ -68,6 +69,7 @@ __device__ inline WaveLDS carve(unsigned char *base, int NL) {
     L.occ = (unsigned char *)(L.lst + 65 * NL);
     L.hol = L.occ + 64;
     L.wg = (short *)(L.hol + 64);
+    L.bw = (unsigned char *)(L.wg + 72);
     L.NL = NL;
     return L;
 }
@@ -213,6 +215,47 @@ __device__ void group_setup(const DevProblem &P, const WalkerCtx &W, const WaveL
             lst[k++] = table_find(P.xtab, x & ~(1ull << r));
         }
     }
+}
+
+// phases of excitations from the walker, from its below-table
+__device__ __forceinline__ double wphase_single(const WaveLDS &L, int gP, int gQ) {
+    int e = L.bw[gP] + L.bw[gQ] - (gP < gQ);
+    return (e & 1) ? -1.0 : 1.0;
+}
+__device__ __forceinline__ double wphase_double(const WaveLDS &L, int P1, int P2, int Q1, int Q2) {
+    int e = L.bw[P1] + L.bw[P2] - (P1 < P2) + L.bw[Q2] - (P1 < Q2) - (P2 < Q2) + L.bw[Q1] - (P1 < Q1) - (P2 < Q1) +
+            (Q2 < Q1);
+    return (e & 1) ? -1.0 : 1.0;
+}
+
+// single P -> Q from the walker: returns the element with every non-core
+// electron in the sum; *act receives the sum over active electrons only
+// (Dyall's H_0)
+__device__ __forceinline__ double single_elem_w2(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, int gP,
+                                                 int gQ, double *act) {
+    int p = g_idx(P, gP), q = g_idx(P, gQ), sp = g_spin(P, gP);
+    double v = P.heff[q * P.Np + p];
+#pragma unroll 4
+    for (int i = 0; i < W.ne; i++) {
+        int gJ = L.wg[i];
+        int j = g_idx(P, gJ);
+        double J = eri4(P, j, j, p, q);
+        double K = eri4(P, p, j, j, q);
+        double t = J - (g_spin(P, gJ) == sp ? K : 0.0);
+        v += (gJ == gP) ? 0.0 : t;
+    }
+    *act = v;
+#pragma unroll
+    for (int i = 0; i < 2; i++) {
+        if (i >= W.n.nv) break;
+        int gJ = W.n.vg[i];
+        if (gJ == gP) continue;
+        int j = g_idx(P, gJ);
+        double J = eri4(P, j, j, p, q);
+        double K = (g_spin(P, gJ) == sp) ? eri4(P, p, j, j, q) : 0.0;
+        v += J - K;
+    }
+    return v;
 }
 
 // h_eff[Q][P] + sum_{J in occ, J != P} [(QP|JJ) - delta_spin (QJ|JP)] over the
@@ -424,12 +467,13 @@ __device__ __forceinline__ void row_eval(const DevProblem &P, const WalkerCtx &W
     o.hd = 0.0;
     o.ok = true;
     if (nP == 1) {
-        double ph = phase_single(P, W.n, Pr0, Qa0);
+        double ph = wphase_single(L, Pr0, Qa0);
+        double act;
         o.phase = ph;
-        o.hnm = ph * single_elem_w(P, L, W.nocc, Pr0, Qa0);
-        if (o.same && P.mode == 1) o.hd = ph * single_elem_w(P, L, W.ne, Pr0, Qa0);
+        o.hnm = ph * single_elem_w2(P, W, L, Pr0, Qa0, &act);
+        o.hd = ph * act;
     } else {
-        double ph = phase_double(P, W.n, Pr0, Pr1, Qa0, Qa1);
+        double ph = wphase_double(L, Pr0, Pr1, Qa0, Qa1);
         o.phase = ph;
         o.hnm = ph * double_elem(P, Pr0, Pr1, Qa0, Qa1);
         o.hd = o.hnm;
@@ -495,6 +539,7 @@ __device__ inline void walker_setup(const DevProblem &P, const WaveLDS &L, int l
     else if (lane < W.ne) L.wg[lane] = (short)g_of_active(P, L.occ[32 + lane - W.e[0]]);
     else if (lane == W.ne && W.n.nv > 0) L.wg[lane] = (short)W.n.vg[0];
     else if (lane == W.ne + 1 && W.n.nv > 1) L.wg[lane] = (short)W.n.vg[1];
+    for (int g = lane; g < 2 * P.Np; g += WAVE) L.bw[g] = (unsigned char)below(P, W.n, g);
     __syncwarp();
 }
 
@@ -719,7 +764,7 @@ __device__ __forceinline__ long long class_of_virt(const DevProblem &P, unsigned
     return class_id2(P.V, (int)v0, (int)v1);
 }
 
-__global__ __launch_bounds__(256) void k_sample(DevProblem P, WalkerArrays S, long long W, long long step0, int nsteps,
+__global__ __launch_bounds__(256, 5) void k_sample(DevProblem P, WalkerArrays S, long long W, long long step0, int nsteps,
                                                 long long burn_in, int NL) {
     extern __shared__ unsigned char smem[];
     int wave = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
@@ -769,7 +814,7 @@ __global__ __launch_bounds__(256) void k_sample(DevProblem P, WalkerArrays S, lo
 }
 
 // local energies without moving (parity / snapshots)
-__global__ __launch_bounds__(256) void k_eval(DevProblem P, const unsigned long long *keys, const unsigned *virts,
+__global__ __launch_bounds__(256, 5) void k_eval(DevProblem P, const unsigned long long *keys, const unsigned *virts,
                                               const int *valid, long long n, int NL, double *eloc, double *psi_out,
                                               double *gamma, double *elocd, int *cls_out) {
     extern __shared__ unsigned char smem[];
