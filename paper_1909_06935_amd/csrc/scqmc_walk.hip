@@ -7,20 +7,24 @@
 // spin-orbitals, Pa: up to two added).  Members of a group differ only in the
 // virtual occupation l_m, i.e. the SC class.  Groups are swept in "blocks"
 // fixed by the spin kinds of Ra and Pa (none, a, b, aa, ab, bb each): inside a
-// block every group has the same number of rows (virtual sets reachable by at
-// most a double excitation) and the same overlap type, so the wave processes
-// a block without divergence:
-//   1. 64 groups at a time, one per lane: decode (Ra, Pa), form x_m and do the
-//      group's reference-table lookups once
+// block every group has the same R rows (virtual sets reachable by at most a
+// double excitation), in the same order, and the same overlap type.
+//   * 64 groups at a time, one per lane: decode (Ra, Pa), form x_m and do the
+//     group's reference-table lookups once
 //        l_m empty      : phi0(x_m)                       (reference table)
 //        one virtual    : y-list of x_m, x-lists of x_m - r for each electron r
 //        two virtuals   : x-list of x_m
-//      (a y-list / x-list holds the reference determinants a determinant with
-//      one / two active electrons removed came from, with their coefficients);
-//   2. all lanes sweep the 64 x R rows: H_nm (Slater-Condon with phase) and
-//      psi(m) = c_l <m|H|phi0> summed over the group's lists, i.e. over
-//      nonzero reference terms only;
-//   3. per-group rate sums by a segmented scan in registers (fixed order).
+//     (a y-list / x-list holds the reference determinants a determinant with
+//     one / two active electrons removed came from, with their coefficients
+//     pre-multiplied by the parity of that removal);
+//   * every group is given a sub-wave of S = 2^k >= min(R, 64) lanes; a lane's
+//     row index is the same for every group of the block, so its row decode
+//     (virtual set, class, SC coefficient) is done once per block (per 64-row
+//     tile when R > 64) and reused for every group;
+//   * a row costs H_nm (Slater-Condon, phase from a per-walker LDS table) and
+//     psi(m) = c_l <m|H|phi0> summed over the group's lists, i.e. over nonzero
+//     reference terms only; per-group rate sums are sub-wave reductions in a
+//     fixed order.
 // The next state: first-reaction method at two levels (exponential clocks keyed
 // by (walker, step, x_m), then by (walker, step, class)) -- independent of the
 // visiting order.
@@ -43,8 +47,7 @@ struct GroupInfo {
     unsigned long long xkey;
     double phi;           // phi0(x_m) for groups without virtual electrons
     double gam;           // sum over rows of |psi(m)|
-    signed char ra[2], pa[2];
-    int pad;
+    short rg[2], pg[2];   // removed / added active spin-orbitals (g codes, -1 if absent)
 };
 
 struct WaveLDS {
@@ -76,7 +79,7 @@ __device__ inline WaveLDS carve(unsigned char *base, int NL) {
 
 struct WalkerCtx {
     NDet n;
-    int vcode[2];   // virtual codes, ascending
+    int vcode[2];   // virtual codes, ascending (-1 absent)
     int vs[2];      // virtual electrons per spin
     int e[2], h[2]; // active electrons / holes per spin
     int ne, nocc;   // active electrons, all non-core electrons
@@ -98,11 +101,11 @@ __device__ __forceinline__ unsigned binom012(int n, int k) {
     return (unsigned)(n * (n - 1) / 2);
 }
 
-// pair index k -> (i < j), k = j(j-1)/2 + i
+// pair index k -> (i < j), k = j(j-1)/2 + i  (float estimate, one correction)
 __device__ __forceinline__ void pair_decode(unsigned k, int &i, int &j) {
     int jj = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)k)) * 0.5f);
-    while (jj * (jj - 1) / 2 > (int)k) jj--;
-    while ((jj + 1) * jj / 2 <= (int)k) jj++;
+    jj -= (jj * (jj - 1) / 2 > (int)k);
+    jj += ((jj + 1) * jj / 2 <= (int)k);
     j = jj;
     i = (int)k - jj * (jj - 1) / 2;
 }
@@ -137,15 +140,10 @@ __device__ __forceinline__ int kind_decode(int k, unsigned idx, const unsigned c
 // k-th virtual orbital of spin sg not occupied by the walker -> virtual code
 __device__ __forceinline__ int avail_virtual(const DevProblem &P, const WalkerCtx &W, int sg, int k) {
     int a = k, lo = sg * P.V;
-    // the walker's virtual codes are ascending (absent = -1, never in range)
-    int c0 = W.vcode[0] - lo, c1 = W.vcode[1] - lo;
+    int c0 = W.vcode[0] - lo, c1 = W.vcode[1] - lo;   // ascending; absent (-1) never in range
     if (W.vcode[0] >= lo && c0 < P.V && c0 <= a) a++;
     if (W.vcode[1] >= lo && c1 < P.V && c1 <= a) a++;
     return lo + a;
-}
-
-__device__ __forceinline__ void sort2(int *v, int n) {
-    if (n == 2 && v[0] > v[1]) { int t = v[0]; v[0] = v[1]; v[1] = t; }
 }
 
 __device__ bool block_setup(const DevProblem &P, const WalkerCtx &W, int rk, int pk, Block &b) {
@@ -195,8 +193,10 @@ __device__ void group_setup(const DevProblem &P, const WalkerCtx &W, const WaveL
     if (pa0 >= 0) x |= 1ull << pa0;
     if (pa1 >= 0) x |= 1ull << pa1;
     G.xkey = x;
-    G.ra[0] = (signed char)ra0; G.ra[1] = (signed char)ra1;
-    G.pa[0] = (signed char)pa0; G.pa[1] = (signed char)pa1;
+    G.rg[0] = (short)(ra0 >= 0 ? g_of_active(P, ra0) : -1);
+    G.rg[1] = (short)(ra1 >= 0 ? g_of_active(P, ra1) : -1);
+    G.pg[0] = (short)(pa0 >= 0 ? g_of_active(P, pa0) : -1);
+    G.pg[1] = (short)(pa1 >= 0 ? g_of_active(P, pa1) : -1);
     G.gam = 0.0;
     G.phi = 0.0;
     int vp = b.vp[0] + b.vp[1];
@@ -258,29 +258,12 @@ __device__ __forceinline__ double single_elem_w2(const DevProblem &P, const Walk
     return v;
 }
 
-// h_eff[Q][P] + sum_{J in occ, J != P} [(QP|JJ) - delta_spin (QJ|JP)] over the
-// walker's occupied list (first `n` entries of wg), independent loads
-__device__ __forceinline__ double single_elem_w(const DevProblem &P, const WaveLDS &L, int n, int gP, int gQ) {
-    int p = g_idx(P, gP), q = g_idx(P, gQ), sp = g_spin(P, gP);
-    double v = P.heff[q * P.Np + p];
-#pragma unroll 4
-    for (int i = 0; i < n; i++) {
-        int gJ = L.wg[i];
-        int j = g_idx(P, gJ);
-        double J = eri4(P, j, j, p, q);
-        double K = eri4(P, p, j, j, q);
-        double t = J - (g_spin(P, gJ) == sp ? K : 0.0);
-        v += (gJ == gP) ? 0.0 : t;
-    }
-    return v;
-}
-
 // h_eff[s][t] + sum_{j in y} [(st|jj) - delta (sj|jt)] with y = x_n - Ra + Pa,
 // iterated as the walker's active electrons minus Ra plus Pa
 __device__ __forceinline__ double fock_y(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L,
                                          const GroupInfo &G, int gT, int gS) {
     int t = g_idx(P, gT), s = g_idx(P, gS), st = g_spin(P, gT);
-    int r0 = G.ra[0] >= 0 ? g_of_active(P, G.ra[0]) : -1, r1 = G.ra[1] >= 0 ? g_of_active(P, G.ra[1]) : -1;
+    int r0 = G.rg[0], r1 = G.rg[1];
     double v = P.heff[s * P.Np + t];
 #pragma unroll 4
     for (int i = 0; i < W.ne; i++) {
@@ -291,9 +274,10 @@ __device__ __forceinline__ double fock_y(const DevProblem &P, const WalkerCtx &W
         double x = J - (g_spin(P, gJ) == st ? K : 0.0);
         v += (gJ == r0 || gJ == r1) ? 0.0 : x;
     }
+#pragma unroll
     for (int i = 0; i < 2; i++) {
-        if (G.pa[i] < 0) continue;
-        int gJ = g_of_active(P, G.pa[i]);
+        int gJ = G.pg[i];
+        if (gJ < 0) continue;
         int j = g_idx(P, gJ);
         double J = eri4(P, j, j, t, s);
         double K = (g_spin(P, gJ) == st) ? eri4(P, t, j, j, s) : 0.0;
@@ -345,7 +329,7 @@ __device__ double phi1(const DevProblem &P, unsigned long long y, int s, ListFn 
 }
 
 // <m|H|phi0> for m = x + virtuals s1 < s2, from the x-list of x (signed coefficients)
-__device__ double phi2(const DevProblem &P, int s1, int s2, uint2 ox) {
+__device__ __forceinline__ double phi2(const DevProblem &P, int s1, int s2, uint2 ox) {
     int sg1 = s1 >= P.V, sg2 = s2 >= P.V;
     int a1 = P.A + s1 - sg1 * P.V, a2 = P.A + s2 - sg2 * P.V;
     double acc = 0.0;
@@ -396,25 +380,27 @@ __device__ double psi_direct(const DevProblem &P, unsigned long long key, unsign
     return P.ccls[class_id2(P.V, vcode[0], vcode[1])] * phi2(P, vcode[0], vcode[1], table_find(P.xtab, key));
 }
 
-struct RowRes {
-    double hnm, psi, hd, phase;
-    long long cls;
-    unsigned virt;
-    bool ok, same;
+// Row r of a block, independent of the group: the virtual set of m, its
+// class and SC coefficient, and the virtual parts of the excitation n -> m.
+struct RowDec {
+    int Lp0, Lp1;        // virtual codes of m (ascending, -1 absent)
+    int rv0, rv1;        // removed virtual electrons (g codes, -1 absent)
+    int ad0, ad1;        // added virtual electrons (g codes, -1 absent)
+    double c;            // SC coefficient of m's class
+    int cls;
+    bool same;           // m keeps the walker's virtual set
 };
 
-// row r of group G in block b
-template <int VP>
-__device__ __forceinline__ void row_eval(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, const Block &b,
-                                         const GroupInfo &G, const uint2 *lst, unsigned r, RowRes &o) {
+__device__ __forceinline__ void row_decode(const DevProblem &P, const WalkerCtx &W, const Block &b, unsigned r,
+                                           RowDec &d) {
     int km = 0;
     unsigned start = 0;
     if (r >= b.fam_end[0]) { km = 1; start = b.fam_end[0]; }
     if (r >= b.fam_end[1]) { km = 2; start = b.fam_end[1]; }
     if (r >= b.fam_end[2]) { km = 3; start = b.fam_end[2]; }
     r -= start;
-    // kept (kc*) and removed (rm*) virtual electrons of the walker
-    int kc0 = -1, kc1 = -1, nk = 0, k0 = 0, k1 = 0, rm0 = -1, rm1 = -1, nrmv = 0;
+    int kc0 = -1, kc1 = -1, nk = 0, k0 = 0, k1 = 0;
+    d.rv0 = d.rv1 = -1;
 #pragma unroll
     for (int i = 0; i < 2; i++) {
         if (i >= W.n.nv) break;
@@ -424,49 +410,63 @@ __device__ __forceinline__ void row_eval(const DevProblem &P, const WalkerCtx &W
             nk++;
             if (c >= P.V) k1++; else k0++;
         } else {
-            if (nrmv == 0) rm0 = c; else rm1 = c;
-            nrmv++;
+            int g = W.n.vg[i];
+            if (d.rv0 < 0) d.rv0 = g; else d.rv1 = g;
         }
     }
-    // added virtual electrons
-    int ad0 = -1, ad1 = -1, nad = 0;
-    if (VP > 0) {
-        int a0 = b.vp[0] - k0, a1 = b.vp[1] - k1;
+    int a0 = b.vp[0] - k0, a1 = b.vp[1] - k1;
+    int x0 = -1, x1 = -1, nad = 0;   // added virtual codes
+    if (a0 + a1 > 0) {
         unsigned c1 = binom012(P.V - W.vs[1], a1);
-        unsigned i0 = r / c1, i1 = r - i0 * c1;
-        if (a0 == 1) { ad0 = avail_virtual(P, W, 0, (int)i0); nad = 1; }
-        else if (a0 == 2) { int i, j; pair_decode(i0, i, j); ad0 = avail_virtual(P, W, 0, i); ad1 = avail_virtual(P, W, 0, j); nad = 2; }
-        if (a1 == 1) { int v = avail_virtual(P, W, 1, (int)i1); if (nad == 0) ad0 = v; else ad1 = v; nad++; }
-        else if (a1 == 2) { int i, j; pair_decode(i1, i, j); ad0 = avail_virtual(P, W, 1, i); ad1 = avail_virtual(P, W, 1, j); nad = 2; }
+        unsigned i0 = (unsigned)((float)r / (float)c1);
+        i0 -= (i0 * c1 > r);
+        i0 += ((i0 + 1) * c1 <= r);
+        unsigned i1 = r - i0 * c1;
+        if (a0 == 1) { x0 = avail_virtual(P, W, 0, (int)i0); nad = 1; }
+        else if (a0 == 2) { int i, j; pair_decode(i0, i, j); x0 = avail_virtual(P, W, 0, i); x1 = avail_virtual(P, W, 0, j); nad = 2; }
+        if (a1 == 1) { int v = avail_virtual(P, W, 1, (int)i1); if (nad == 0) x0 = v; else x1 = v; nad++; }
+        else if (a1 == 2) { int i, j; pair_decode(i1, i, j); x0 = avail_virtual(P, W, 1, i); x1 = avail_virtual(P, W, 1, j); nad = 2; }
     }
-    // virtual set of m (ascending)
-    int Lp0 = -1, Lp1 = -1;
-    if (VP == 1) {
-        Lp0 = nk ? kc0 : ad0;
-    } else if (VP == 2) {
-        int x0 = nk > 0 ? kc0 : ad0;
-        int x1 = nk > 1 ? kc1 : (nk == 1 ? ad0 : ad1);
-        Lp0 = x0 < x1 ? x0 : x1;
-        Lp1 = x0 < x1 ? x1 : x0;
+    d.ad0 = x0 >= 0 ? g_of_virtual(P, x0) : -1;
+    d.ad1 = x1 >= 0 ? g_of_virtual(P, x1) : -1;
+    int vp = b.vp[0] + b.vp[1];
+    if (vp == 0) {
+        d.Lp0 = d.Lp1 = -1;
+        d.cls = 0;
+    } else if (vp == 1) {
+        d.Lp0 = nk ? kc0 : x0;
+        d.Lp1 = -1;
+        d.cls = 1 + d.Lp0;
+    } else {
+        int y0 = nk > 0 ? kc0 : x0;
+        int y1 = nk > 1 ? kc1 : (nk == 1 ? x0 : x1);
+        d.Lp0 = y0 < y1 ? y0 : y1;
+        d.Lp1 = y0 < y1 ? y1 : y0;
+        int V2 = 2 * P.V;
+        d.cls = 1 + V2 + d.Lp0 * V2 - d.Lp0 * (d.Lp0 + 1) / 2 + (d.Lp1 - d.Lp0 - 1);
     }
-    o.cls = VP == 0 ? 0 : (VP == 1 ? class_id1(P.V, Lp0) : class_id2(P.V, Lp0, Lp1));
-    o.virt = (VP > 0 ? (unsigned)Lp0 : SCQ_NOVIRT) | ((VP > 1 ? (unsigned)Lp1 : SCQ_NOVIRT) << 16);
-    o.same = (nad == 0 && nk == W.n.nv);
+    d.c = P.ccls[d.cls];
+    d.same = (nad == 0 && nk == W.n.nv);
+}
+
+struct RowRes {
+    double hnm, psi, hd, phase;
+    bool ok;
+};
+
+// row d of group G: <m|H|n>, psi(m), the Dyall element if m keeps n's virtual set
+template <int VP>
+__device__ __forceinline__ void row_eval(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L,
+                                         const RowDec &d, const GroupInfo &G, const uint2 *lst, RowRes &o) {
     // outer excitation n -> m: removed P*, added Q* (ascending spin-orbital order)
-    int Pr0 = -1, Pr1 = -1, nP = 0, Qa0 = -1, Qa1 = -1, nQ = 0;
-    if (G.ra[0] >= 0) { Pr0 = g_of_active(P, G.ra[0]); nP = 1; }
-    if (G.ra[1] >= 0) { Pr1 = g_of_active(P, G.ra[1]); nP = 2; }
-    if (nrmv > 0) { int v = g_of_virtual(P, rm0); if (nP == 0) Pr0 = v; else Pr1 = v; nP++; }
-    if (nrmv > 1) { Pr1 = g_of_virtual(P, rm1); nP = 2; }
-    if (G.pa[0] >= 0) { Qa0 = g_of_active(P, G.pa[0]); nQ = 1; }
-    if (G.pa[1] >= 0) { Qa1 = g_of_active(P, G.pa[1]); nQ = 2; }
-    if (nad > 0) { int v = g_of_virtual(P, ad0); if (nQ == 0) Qa0 = v; else Qa1 = v; nQ++; }
-    if (nad > 1) { Qa1 = g_of_virtual(P, ad1); nQ = 2; }
-    if (nP == 2 && Pr0 > Pr1) { int t = Pr0; Pr0 = Pr1; Pr1 = t; }
-    if (nQ == 2 && Qa0 > Qa1) { int t = Qa0; Qa0 = Qa1; Qa1 = t; }
-    o.hd = 0.0;
+    int Pr0 = G.rg[0], Pr1 = G.rg[1], Qa0 = G.pg[0], Qa1 = G.pg[1];
+    if (Pr0 < 0) { Pr0 = d.rv0; Pr1 = d.rv1; } else if (Pr1 < 0) Pr1 = d.rv0;
+    if (Qa0 < 0) { Qa0 = d.ad0; Qa1 = d.ad1; } else if (Qa1 < 0) Qa1 = d.ad0;
+    if (Pr1 >= 0 && Pr0 > Pr1) { int t = Pr0; Pr0 = Pr1; Pr1 = t; }
+    if (Qa1 >= 0 && Qa0 > Qa1) { int t = Qa0; Qa0 = Qa1; Qa1 = t; }
     o.ok = true;
-    if (nP == 1) {
+    o.hd = 0.0;
+    if (Pr1 < 0) {
         double ph = wphase_single(L, Pr0, Qa0);
         double act;
         o.phase = ph;
@@ -483,21 +483,19 @@ __device__ __forceinline__ void row_eval(const DevProblem &P, const WalkerCtx &W
     if (VP == 0) {
         phi = G.phi;
     } else if (VP == 1) {
-        phi = phi1(P, G.xkey, Lp0, [&](int k) -> uint2 { return lst[k]; },
+        phi = phi1(P, G.xkey, d.Lp0, [&](int k) -> uint2 { return lst[k]; },
                    [&](int gT, int gS) -> double { return fock_y(P, W, L, G, gT, gS); });
     } else {
-        phi = phi2(P, Lp0, Lp1, lst[0]);
+        phi = phi2(P, d.Lp0, d.Lp1, lst[0]);
     }
-    o.psi = P.ccls[o.cls] * phi;
+    o.psi = d.c * phi;
 }
 
-// out-of-line row evaluation for the cold paths (selected group, debug listing)
-__device__ __forceinline__ void row_eval_any(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, const Block &b,
-                                          const GroupInfo &G, const uint2 *lst, unsigned r, RowRes &o) {
-    int vp = b.vp[0] + b.vp[1];
-    if (vp == 0) row_eval<0>(P, W, L, b, G, lst, r, o);
-    else if (vp == 1) row_eval<1>(P, W, L, b, G, lst, r, o);
-    else row_eval<2>(P, W, L, b, G, lst, r, o);
+__device__ __forceinline__ void row_eval_any(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, int vp,
+                                             const RowDec &d, const GroupInfo &G, const uint2 *lst, RowRes &o) {
+    if (vp == 0) row_eval<0>(P, W, L, d, G, lst, o);
+    else if (vp == 1) row_eval<1>(P, W, L, d, G, lst, o);
+    else row_eval<2>(P, W, L, d, G, lst, o);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -578,51 +576,54 @@ struct Acc {
     long long bestg;
 };
 
-// sweep one block: groups 64 at a time, rows over all lanes
+// sub-wave sum over S consecutive lanes (S a power of two), fixed tree
+__device__ __forceinline__ double subwave_sum(double v, unsigned S) {
+    for (unsigned d = 1; d < S; d <<= 1) v += __shfl_xor(v, (int)d);
+    return v;
+}
+
+// sweep one block: 64 groups set up at a time, each group owns a sub-wave of
+// S lanes, lane row index r = tile*S + (lane mod S) fixed across groups
 template <bool MOVE>
 __device__ void sweep_block(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, int lane, const Block &b,
                             uint32_t wid, uint32_t step, bool dy, Acc &a) {
     GroupInfo &mg = L.G[lane];
     uint2 *mlst = L.lst + lane * L.NL;
-    float invR = 1.0f / (float)b.R;
+    unsigned S = 1;
+    while (S < b.R && S < WAVE) S <<= 1;
+    int sh = __ffs(S) - 1;
+    unsigned gpi = WAVE >> sh;                 // groups per pass
+    unsigned ntile = (b.R + S - 1) >> sh;      // > 1 only when R > 64
+    unsigned sub = (unsigned)lane & (S - 1), grp = (unsigned)lane >> sh;
+    int vp = b.vp[0] + b.vp[1];
+    RowDec d;
+    if (ntile == 1 && sub < b.R) row_decode(P, W, b, sub, d);
     for (long long gb = 0; gb < b.ng; gb += WAVE) {
         long long g = gb + lane;
         unsigned ngc = (unsigned)min((long long)WAVE, b.ng - gb);
         if (g < b.ng) group_setup(P, W, L, b, g, mg, mlst);
         __syncwarp();
-        unsigned T = ngc * b.R;
-        for (unsigned fb = 0; fb < T; fb += WAVE) {
-            unsigned f = fb + (unsigned)lane;
-            int gi = WAVE;
-            double v = 0.0;
-            if (f < T) {
-                unsigned q = (unsigned)((float)f * invR);
-                if (q * b.R > f) q--;
-                if ((q + 1) * b.R <= f) q++;
-                gi = (int)q;
-                RowRes o;
-                row_eval_any(P, W, L, b, L.G[gi], L.lst + gi * L.NL, f - q * b.R, o);
-                if (o.ok) {
-                    a.E += o.hnm * o.psi;
-                    v = fabs(o.psi);
-                    a.G += v;
-                    if (dy && o.same) a.D += o.hd * o.psi;
+        for (unsigned t = 0; t < ntile; t++) {
+            unsigned r = t * S + sub;
+            bool rv = r < b.R;
+            if (ntile > 1 && rv) row_decode(P, W, b, r, d);
+            for (unsigned gp = 0; gp < ngc; gp += gpi) {
+                unsigned gi = gp + grp;
+                double v = 0.0;
+                if (rv && gi < ngc) {
+                    RowRes o;
+                    row_eval_any(P, W, L, vp, d, L.G[gi], L.lst + gi * L.NL, o);
+                    if (o.ok) {
+                        a.E += o.hnm * o.psi;
+                        v = fabs(o.psi);
+                        a.G += v;
+                        if (dy && d.same) a.D += o.hd * o.psi;
+                    }
                 }
+                v = subwave_sum(v, S);
+                if (sub == 0 && gi < ngc) L.G[gi].gam += v;
+                __syncwarp();
             }
-            if (b.R == 1) {
-                if (gi < WAVE) L.G[gi].gam += v;
-            } else {
-#pragma unroll
-                for (int d = 1; d < WAVE; d <<= 1) {
-                    double ov = __shfl_up(v, d);
-                    int og = __shfl_up(gi, d);
-                    if (lane >= d && og == gi) v += ov;
-                }
-                int ng = __shfl_down(gi, 1);
-                bool last = (lane == WAVE - 1) || (ng != gi);
-                if (last && gi < WAVE) L.G[gi].gam += v;
-            }
-            __syncwarp();
         }
         if (MOVE && g < b.ng && mg.gam > 0.0) {
             double tau = exp_draw(P.seed, wid, step, 0u, (uint32_t)mg.xkey, (uint32_t)(mg.xkey >> 32)) / mg.gam;
@@ -688,21 +689,29 @@ __device__ void walker_eval(const DevProblem &P, const WaveLDS &L, int lane, uns
     uint2 *slst = L.lst + WAVE * L.NL;
     if (lane == 0) group_setup(P, W, L, b, a.bestg, sg, slst);
     __syncwarp();
+    int vp = b.vp[0] + b.vp[1];
     double b2 = INFINITY;
-    long long bcls = 0x7fffffffffffffffLL;
+    int bcls = 0x7fffffff;
     double bpsi = 0.0;
     unsigned bvirt = 0;
     for (unsigned r = lane; r < b.R; r += WAVE) {
+        RowDec d;
+        row_decode(P, W, b, r, d);
         RowRes o;
-        row_eval_any(P, W, L, b, sg, slst, r, o);
+        row_eval_any(P, W, L, vp, d, sg, slst, o);
         if (!o.ok || o.psi == 0.0) continue;
-        double tau = exp_draw(P.seed, wid, step, 1u, (uint32_t)o.cls, 0u) / fabs(o.psi);
-        if (tau < b2 || (tau == b2 && o.cls < bcls)) { b2 = tau; bcls = o.cls; bpsi = o.psi; bvirt = o.virt; }
+        double tau = exp_draw(P.seed, wid, step, 1u, (uint32_t)d.cls, 0u) / fabs(o.psi);
+        if (tau < b2 || (tau == b2 && d.cls < bcls)) {
+            b2 = tau;
+            bcls = d.cls;
+            bpsi = o.psi;
+            bvirt = (d.Lp0 >= 0 ? (unsigned)d.Lp0 : SCQ_NOVIRT) | ((d.Lp1 >= 0 ? (unsigned)d.Lp1 : SCQ_NOVIRT) << 16);
+        }
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
         double ob = __shfl_xor(b2, d);
-        long long oc = __shfl_xor(bcls, d);
+        int oc = __shfl_xor(bcls, d);
         double op = __shfl_xor(bpsi, d);
         unsigned ov = __shfl_xor(bvirt, d);
         if (ob < b2 || (ob == b2 && oc < bcls)) { b2 = ob; bcls = oc; bpsi = op; bvirt = ov; }
@@ -764,8 +773,8 @@ __device__ __forceinline__ long long class_of_virt(const DevProblem &P, unsigned
     return class_id2(P.V, (int)v0, (int)v1);
 }
 
-__global__ __launch_bounds__(256, 5) void k_sample(DevProblem P, WalkerArrays S, long long W, long long step0, int nsteps,
-                                                long long burn_in, int NL) {
+__global__ __launch_bounds__(256, 4) void k_sample(DevProblem P, WalkerArrays S, long long W, long long step0,
+                                                   int nsteps, long long burn_in, int NL) {
     extern __shared__ unsigned char smem[];
     int wave = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     long long w = (long long)blockIdx.x * WPB + wave;
@@ -814,9 +823,9 @@ __global__ __launch_bounds__(256, 5) void k_sample(DevProblem P, WalkerArrays S,
 }
 
 // local energies without moving (parity / snapshots)
-__global__ __launch_bounds__(256, 5) void k_eval(DevProblem P, const unsigned long long *keys, const unsigned *virts,
-                                              const int *valid, long long n, int NL, double *eloc, double *psi_out,
-                                              double *gamma, double *elocd, int *cls_out) {
+__global__ __launch_bounds__(256, 4) void k_eval(DevProblem P, const unsigned long long *keys, const unsigned *virts,
+                                                 const int *valid, long long n, int NL, double *eloc, double *psi_out,
+                                                 double *gamma, double *elocd, int *cls_out) {
     extern __shared__ unsigned char smem[];
     int wave = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     long long i = (long long)blockIdx.x * WPB + wave;
@@ -851,34 +860,6 @@ __global__ void k_psi(DevProblem P, const unsigned long long *keys, const unsign
 }
 
 // neighbour list of one walker (debug): one wave, groups and rows one lane at a time
-template <int VP>
-__device__ void list_block(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, int lane, const Block &b,
-                           long long cap, unsigned long long *okey, unsigned *ovirt, signed char *ophase, double *ohnm,
-                           double *opsi, unsigned long long *count) {
-    GroupInfo &mg = L.G[lane];
-    uint2 *mlst = L.lst + lane * L.NL;
-    for (long long gb = 0; gb < b.ng; gb += WAVE) {
-        long long g = gb + lane;
-        if (g < b.ng) {
-            group_setup(P, W, L, b, g, mg, mlst);
-            for (unsigned r = 0; r < b.R; r++) {
-                RowRes o;
-                row_eval_any(P, W, L, b, mg, mlst, r, o);
-                if (!o.ok) continue;
-                unsigned long long pos = atomicAdd(count, 1ull);
-                if ((long long)pos < cap) {
-                    okey[pos] = mg.xkey;
-                    ovirt[pos] = o.virt;
-                    ophase[pos] = (signed char)(o.phase > 0 ? 1 : -1);
-                    ohnm[pos] = o.hnm;
-                    opsi[pos] = o.psi;
-                }
-            }
-        }
-        __syncwarp();
-    }
-}
-
 __global__ __launch_bounds__(64) void k_neighbors(DevProblem P, unsigned long long key, unsigned virt, int NL,
                                                   long long cap, unsigned long long *okey, unsigned *ovirt,
                                                   signed char *ophase, double *ohnm, double *opsi,
@@ -893,8 +874,30 @@ __global__ __launch_bounds__(64) void k_neighbors(DevProblem P, unsigned long lo
             Block b;
             if (!block_setup(P, W, rk, pk, b)) continue;
             int vp = b.vp[0] + b.vp[1];
-            if (vp == 0) list_block<0>(P, W, L, lane, b, cap, okey, ovirt, ophase, ohnm, opsi, count);
-            else if (vp == 1) list_block<1>(P, W, L, lane, b, cap, okey, ovirt, ophase, ohnm, opsi, count);
-            else list_block<2>(P, W, L, lane, b, cap, okey, ovirt, ophase, ohnm, opsi, count);
+            GroupInfo &mg = L.G[lane];
+            uint2 *mlst = L.lst + lane * L.NL;
+            for (long long gb = 0; gb < b.ng; gb += WAVE) {
+                long long g = gb + lane;
+                if (g < b.ng) {
+                    group_setup(P, W, L, b, g, mg, mlst);
+                    for (unsigned r = 0; r < b.R; r++) {
+                        RowDec d;
+                        row_decode(P, W, b, r, d);
+                        RowRes o;
+                        row_eval_any(P, W, L, vp, d, mg, mlst, o);
+                        if (!o.ok) continue;
+                        unsigned long long pos = atomicAdd(count, 1ull);
+                        if ((long long)pos < cap) {
+                            okey[pos] = mg.xkey;
+                            ovirt[pos] = (d.Lp0 >= 0 ? (unsigned)d.Lp0 : SCQ_NOVIRT) |
+                                         ((d.Lp1 >= 0 ? (unsigned)d.Lp1 : SCQ_NOVIRT) << 16);
+                            ophase[pos] = (signed char)(o.phase > 0 ? 1 : -1);
+                            ohnm[pos] = o.hnm;
+                            opsi[pos] = o.psi;
+                        }
+                    }
+                }
+                __syncwarp();
+            }
         }
 }
