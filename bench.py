@@ -13,6 +13,11 @@ Prints one JSON line (rank 0, N = 1).  Besides the throughput it carries
                   walker-step reads, counted by the oracle on a sample of the
                   equilibrated walkers, plus walker state) over the launch
                   time measured with HIP events on the kernel's stream;
+                  `traffic` is the measured HBM bytes per launch (rocprofv3
+                  FETCH_SIZE + WRITE_SIZE, copy-calibrated) from the committed
+                  counter summary, reported only while the kernel sources are
+                  the ones it was taken on; `fp64` the same launch time
+                  against the FP64 vector peak with a minimal flop count;
   cpu_baseline -- the CPU oracle on a bounded sample of the same walkers.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config cfg2|cfg3]
@@ -29,6 +34,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
 WALKER_STATE_BYTES = 2 * (8 + 4 + 8 + 24)   # key, virtual codes, psi, per-walker sums; read + write
 
 WORKLOADS = {
@@ -72,14 +78,51 @@ def cpu_baseline(prob, dets, seed, step, budget_s=20.0, threads=None):
                           sample=f"{n} equilibrated walkers x 1 step, {dt:.1f} s on {threads} threads")
 
 
-def algorithmic_bytes(orc, dets, nmax=256):
-    """Mean distinct operand bytes of one walker-step over a sample."""
+def algorithmic_work(orc, dets, nmax=256):
+    """Mean distinct operand bytes and minimal FP64 flops of one walker-step
+    over a sample.  Flops: one multiply-add per nonzero reference term of an
+    overlap, one multiply-add (H_nm psi(m)) and one add (|psi(m)|) per
+    neighbour."""
     from concurrent.futures import ThreadPoolExecutor
     sel = dets[:nmax]
     with ThreadPoolExecutor(max_workers=os.cpu_count()) as ex:
         tr = list(ex.map(orc.traffic, sel))
     per = [8 * x["eri"] + 8 * x["heff"] + 16 * x["ref"] + WALKER_STATE_BYTES for x in tr]
-    return float(np.mean(per)), len(sel)
+    flops = [2 * x["terms"] + 3 * x["n_nbr"] for x in tr]
+    return float(np.mean(per)), float(np.mean(flops)), len(sel)
+
+
+def kernel_source_digest():
+    """sha256 over the HIP sources (name + bytes, sorted by name)."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_1909_06935_amd", "csrc")
+    h = hashlib.sha256()
+    for n in sorted(os.listdir(d)):
+        if n.endswith((".hip", ".h")):
+            h.update(n.encode())
+            with open(os.path.join(d, n), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(config, walker_steps):
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary,
+    or None when the kernel sources changed since the counters were taken or
+    the launch size differs."""
+    path = os.path.join(ROOT, "profiles", f"k_sample_{config}_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            parts = line.strip().split(":", 1)
+            if len(parts) == 2 and parts[0] in ("source_digest", "traffic_bytes_per_launch", "walker_steps_per_launch"):
+                kv[parts[0]] = parts[1].strip()
+    if kv.get("source_digest") != kernel_source_digest():
+        return None
+    if int(kv.get("walker_steps_per_launch", -1)) != walker_steps:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
 
 
 def main():
@@ -163,15 +206,19 @@ def main():
     }
     if not args.no_cpu:
         orc, idx, cb = cpu_baseline(prob, dets, prob.seed_walk, int(steps))
-        per_bytes, nsamp = algorithmic_bytes(orc, dets[idx])
+        per_bytes, per_flops, nsamp = algorithmic_work(orc, dets[idx])
         per_launch = per_bytes * W * args.block
         avg_s = float(np.mean(launch_ms)) * 1e-3
         ach = per_launch / avg_s / 1e9
+        fl = per_flops * W * args.block / avg_s / 1e12
         out["roofline"] = {
             "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-            "traffic": None, "kernel": "k_sample", "avg_launch_ms": avg_s * 1e3,
+            "traffic": measured_traffic(args.config, W * args.block), "kernel": "k_sample",
+            "avg_launch_ms": avg_s * 1e3,
             "bytes_per_walker_step": per_bytes, "walker_steps_per_launch": W * args.block,
             "count_sample": nsamp,
+            "fp64": {"achieved": fl, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": fl / FP64_PEAK_TFLOPS,
+                     "flops_per_walker_step": per_flops},
         }
         out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)

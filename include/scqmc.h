@@ -119,9 +119,9 @@ scqmc_status scqmc_set_integrals_dense(scqmc_ctx *ctx, const double *h1, const d
  * determinants it came from. */
 scqmc_status scqmc_set_reference(scqmc_ctx *ctx, int64_t n_det, const uint64_t *dets, const double *coeff);
 
-/* SC coefficients: c0 for phi0 and c_cls[n-1] for classes 1..n_classes-1
- * (n must equal n_classes).  Zero coefficients are allowed (the class is then
- * never visited). */
+/* SC coefficients: c0 for phi0 and c_cls[n] for classes 1..n_classes-1, in
+ * class-id order (n must equal n_classes - 1, else SCQMC_E_INVALID_ARG).
+ * Zero coefficients are allowed (the class is then never visited). */
 scqmc_status scqmc_set_sc_coeffs(scqmc_ctx *ctx, double c0, const double *c_cls, int64_t n);
 
 /* Dyall Hamiltonian of "SC-NEVPT2(s)": virtual orbital energies eps_virt[V]
