@@ -48,7 +48,19 @@ struct GroupInfo {
     double phi;           // phi0(x_m) for groups without virtual electrons
     double gam;           // sum over rows of |psi(m)|
     short rg[2], pg[2];   // removed / added active spin-orbitals (g codes, -1 if absent)
+    int nl;               // one virtual electron: nonempty x-lists stored after the y-list
+    int live;             // some row of the group can have psi(m) != 0
 };
+
+// Read-only table and integral loads.  With a wave-uniform index (U) they go
+// through the constant address space, so the compiler issues scalar loads;
+// otherwise plain vector loads.  Nothing a launch reads this way is written
+// during the launch.
+template <bool U, class T>
+__device__ __forceinline__ T tload(const T *p, unsigned i) {
+    if (U) return ((const __attribute__((address_space(4))) T *)p)[i];
+    return p[i];
+}
 
 struct WaveLDS {
     GroupInfo *G;          // [65]; slot 64 holds the selected group
@@ -57,11 +69,12 @@ struct WaveLDS {
     unsigned char *hol;    // [2][32] active holes per spin
     short *wg;             // [72] g codes of the walker's occupied non-core spin-orbitals (active, then virtual)
     unsigned char *bw;     // [256] electrons of the walker below each non-core spin-orbital g (phases)
+    unsigned char *perm;   // [64] live groups of the current 64, in order
     int NL;
 };
 
 __host__ __device__ inline size_t wave_lds_bytes(int NL) {
-    size_t b = 65 * sizeof(GroupInfo) + 65 * (size_t)NL * sizeof(uint2) + 128 + 72 * sizeof(short) + 256;
+    size_t b = 65 * sizeof(GroupInfo) + 65 * (size_t)NL * sizeof(uint2) + 128 + 72 * sizeof(short) + 256 + 64;
     return (b + 15) & ~(size_t)15;
 }
 
@@ -73,6 +86,7 @@ __device__ inline WaveLDS carve(unsigned char *base, int NL) {
     L.hol = L.occ + 64;
     L.wg = (short *)(L.hol + 64);
     L.bw = (unsigned char *)(L.wg + 72);
+    L.perm = L.bw + 256;
     L.NL = NL;
     return L;
 }
@@ -180,6 +194,19 @@ __device__ bool block_setup(const DevProblem &P, const WalkerCtx &W, int rk, int
     return tot > 0;
 }
 
+// Hash lookups whose first probe was already loaded (s = slots[slot]): most
+// keys are settled by that one load, so several lookups can have their first
+// loads in flight together; after a collision probing goes on one by one.
+__device__ __forceinline__ uint2 probe_from(const DevTable &t, unsigned long long key, ulonglong2 s,
+                                            unsigned long long slot) {
+    while (true) {
+        if (s.x == key) return make_uint2((unsigned)s.y, (unsigned)(s.y >> 32));
+        if (s.x == SCQ_EMPTY_KEY) return make_uint2(0u, 0u);
+        slot = (slot + 1) & t.mask;
+        s = t.slots[slot];
+    }
+}
+
 // group g of block b: decode (Ra, Pa), form x_m, do the lookups of its overlap type
 __device__ void group_setup(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, const Block &b, long long g,
                             GroupInfo &G, uint2 *lst) {
@@ -199,21 +226,56 @@ __device__ void group_setup(const DevProblem &P, const WalkerCtx &W, const WaveL
     G.pg[1] = (short)(pa1 >= 0 ? g_of_active(P, pa1) : -1);
     G.gam = 0.0;
     G.phi = 0.0;
+    G.nl = 0;
     int vp = b.vp[0] + b.vp[1];
     if (vp == 0) {
         uint2 oc = table_find(P.ref, x);
         G.phi = oc.y ? P.ref.vals[oc.x] : 0.0;
+        G.live = G.phi != 0.0;
     } else if (vp == 2) {
         lst[0] = table_find(P.xtab, x);
+        G.live = lst[0].y != 0;
     } else {
-        lst[0] = table_find(P.ytab, x);
+        // y-list, then the nonempty x-lists of x - r (ascending r; r in the top
+        // byte of .y); first probes issued four at a time
+        unsigned long long hy = scq_hash(x) & P.ytab.mask;
+        ulonglong2 sy = P.ytab.slots[hy];
         int k = 1;
         unsigned long long y = x;
         while (y) {
-            int r = __ffsll((long long)y) - 1;
+            int r0 = __ffsll((long long)y) - 1;
             y &= y - 1ull;
-            lst[k++] = table_find(P.xtab, x & ~(1ull << r));
+            int r1 = y ? __ffsll((long long)y) - 1 : -1;
+            y &= y - 1ull;
+            int r2 = y ? __ffsll((long long)y) - 1 : -1;
+            y &= y - 1ull;
+            int r3 = y ? __ffsll((long long)y) - 1 : -1;
+            y &= y - 1ull;
+            unsigned long long k0 = x & ~(1ull << r0);
+            unsigned long long k1 = r1 >= 0 ? x & ~(1ull << r1) : k0;
+            unsigned long long k2 = r2 >= 0 ? x & ~(1ull << r2) : k0;
+            unsigned long long k3 = r3 >= 0 ? x & ~(1ull << r3) : k0;
+            unsigned long long h0 = scq_hash(k0) & P.xtab.mask, h1 = scq_hash(k1) & P.xtab.mask;
+            unsigned long long h2 = scq_hash(k2) & P.xtab.mask, h3 = scq_hash(k3) & P.xtab.mask;
+            ulonglong2 s0 = P.xtab.slots[h0], s1 = P.xtab.slots[h1], s2 = P.xtab.slots[h2], s3 = P.xtab.slots[h3];
+            uint2 o = probe_from(P.xtab, k0, s0, h0);
+            if (o.y) lst[k++] = make_uint2(o.x, o.y | ((unsigned)r0 << 24));
+            if (r1 >= 0) {
+                o = probe_from(P.xtab, k1, s1, h1);
+                if (o.y) lst[k++] = make_uint2(o.x, o.y | ((unsigned)r1 << 24));
+            }
+            if (r2 >= 0) {
+                o = probe_from(P.xtab, k2, s2, h2);
+                if (o.y) lst[k++] = make_uint2(o.x, o.y | ((unsigned)r2 << 24));
+            }
+            if (r3 >= 0) {
+                o = probe_from(P.xtab, k3, s3, h3);
+                if (o.y) lst[k++] = make_uint2(o.x, o.y | ((unsigned)r3 << 24));
+            }
         }
+        lst[0] = probe_from(P.ytab, x, sy, hy);
+        G.nl = k - 1;
+        G.live = (lst[0].y != 0) || k > 1;
     }
 }
 
@@ -260,10 +322,9 @@ __device__ __forceinline__ double single_elem_w2(const DevProblem &P, const Walk
 
 // h_eff[s][t] + sum_{j in y} [(st|jj) - delta (sj|jt)] with y = x_n - Ra + Pa,
 // iterated as the walker's active electrons minus Ra plus Pa
-__device__ __forceinline__ double fock_y(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L,
-                                         const GroupInfo &G, int gT, int gS) {
+__device__ __forceinline__ double fock_y(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, int r0,
+                                         int r1, int p0, int p1, int gT, int gS) {
     int t = g_idx(P, gT), s = g_idx(P, gS), st = g_spin(P, gT);
-    int r0 = G.rg[0], r1 = G.rg[1];
     double v = P.heff[s * P.Np + t];
 #pragma unroll 4
     for (int i = 0; i < W.ne; i++) {
@@ -276,7 +337,7 @@ __device__ __forceinline__ double fock_y(const DevProblem &P, const WalkerCtx &W
     }
 #pragma unroll
     for (int i = 0; i < 2; i++) {
-        int gJ = G.pg[i];
+        int gJ = i ? p1 : p0;
         if (gJ < 0) continue;
         int j = g_idx(P, gJ);
         double J = eri4(P, j, j, t, s);
@@ -290,33 +351,33 @@ __device__ __forceinline__ double fock_y(const DevProblem &P, const WalkerCtx &W
 // Slater-Condon phase that depends on the reference determinant (the
 // annihilation of its removed electrons); the rest depends on spins and on the
 // electron r only.  `fock` gives the single-excitation element.
-template <class ListFn, class FockFn>
-__device__ double phi1(const DevProblem &P, unsigned long long y, int s, ListFn lists, FockFn fock) {
+// lists(0) is the y-list of y; lists(1..nl) are x-lists of y - r with r in
+// the top byte of .y (ascending r; empty ones may be left out).
+template <bool U, class ListFn, class FockFn>
+__device__ double phi1(const DevProblem &P, unsigned long long y, int s, int nl, ListFn lists, FockFn fock) {
     int sg = s >= P.V;
     int gs = g_of_virtual(P, s);
     int bs = sg ? P.nea + P.neb : P.nea;   // electrons below s in any active-space determinant
     double acc1 = 0.0;
     uint2 oc = lists(0);
     for (unsigned k = 0; k < oc.y; k++) {
-        int t = (int)P.ytab.codes[oc.x + k];
-        acc1 += P.ytab.vals[oc.x + k] * fock(g_of_active(P, t), gs);
+        int t = (int)tload<U>(P.ytab.codes, oc.x + k);
+        acc1 += tload<U>(P.ytab.vals, oc.x + k) * fock(g_of_active(P, t), gs);
     }
     double acc = ((bs - 1) & 1) ? -acc1 : acc1;
-    unsigned long long yy = y;
-    int li = 1;
-    while (yy) {
-        int r = __ffsll((long long)yy) - 1;
-        yy &= yy - 1ull;
-        uint2 ox = lists(li++);
-        if (!ox.y) continue;
+    for (int li = 1; li <= nl; li++) {
+        uint2 ox = lists(li);
+        unsigned cnt = ox.y & 0xFFFFFFu;
+        if (!cnt) continue;
+        int r = (int)(ox.y >> 24);
         int gr = g_of_active(P, r);
         int Q1 = gs < gr ? gs : gr, Q2 = gs < gr ? gr : gs;
         unsigned long long yr = y & ~(1ull << r);
-        for (unsigned k = 0; k < ox.y; k++) {
-            unsigned code = P.xtab.codes[ox.x + k];
+        for (unsigned k = 0; k < cnt; k++) {
+            unsigned code = tload<U>(P.xtab.codes, ox.x + k);
             int t = (int)(code >> 6), u = (int)(code & 63u);
             if (t == r || u == r) continue;
-            double w = P.xtab.vals[ox.x + k];
+            double w = tload<U>(P.xtab.vals, ox.x + k);
             int P1 = g_of_active(P, t), P2 = g_of_active(P, u);
             int br = key_below(yr | (1ull << t) | (1ull << u), r);
             int b1 = Q1 == gs ? bs : br, b2 = Q2 == gs ? bs : br;
@@ -329,6 +390,7 @@ __device__ double phi1(const DevProblem &P, unsigned long long y, int s, ListFn 
 }
 
 // <m|H|phi0> for m = x + virtuals s1 < s2, from the x-list of x (signed coefficients)
+template <bool U>
 __device__ __forceinline__ double phi2(const DevProblem &P, int s1, int s2, uint2 ox) {
     int sg1 = s1 >= P.V, sg2 = s2 >= P.V;
     int a1 = P.A + s1 - sg1 * P.V, a2 = P.A + s2 - sg2 * P.V;
@@ -336,16 +398,16 @@ __device__ __forceinline__ double phi2(const DevProblem &P, int s1, int s2, uint
     if (sg1 != sg2) {
         // alpha-beta pair: only (s1 t|s2 u) survives; spin part of the phase (-1)^(n_beta + 1)
         for (unsigned k = 0; k < ox.y; k++) {
-            unsigned code = P.xtab.codes[ox.x + k];
+            unsigned code = tload<U>(P.xtab.codes, ox.x + k);
             int t = (int)((code >> 6) & 31u), u = (int)(code & 31u);
-            acc += P.xtab.vals[ox.x + k] * eri4(P, a1, t, a2, u);
+            acc += tload<U>(P.xtab.vals, ox.x + k) * eri4(P, a1, t, a2, u);
         }
         return ((P.neb + 1) & 1) ? -acc : acc;
     }
     for (unsigned k = 0; k < ox.y; k++) {
-        unsigned code = P.xtab.codes[ox.x + k];
+        unsigned code = tload<U>(P.xtab.codes, ox.x + k);
         int t = (int)((code >> 6) & 31u), u = (int)(code & 31u);
-        acc += P.xtab.vals[ox.x + k] * (eri4(P, a1, t, a2, u) - eri4(P, a1, u, a2, t));
+        acc += tload<U>(P.xtab.vals, ox.x + k) * (eri4(P, a1, t, a2, u) - eri4(P, a1, u, a2, t));
     }
     return acc;
 }
@@ -359,14 +421,15 @@ __device__ double psi_direct(const DevProblem &P, unsigned long long key, unsign
         return oc.y ? P.ccls[0] * P.ref.vals[oc.x] : 0.0;
     }
     if (nv == 1) {
-        double phi = phi1(
-            P, key, vcode[0],
+        double phi = phi1<false>(
+            P, key, vcode[0], popc64(key),
             [&](int k) -> uint2 {
                 if (k == 0) return table_find(P.ytab, key);
                 unsigned long long y = key;
                 for (int i = 1; i < k; i++) y &= y - 1ull;
                 int r = __ffsll((long long)y) - 1;
-                return table_find(P.xtab, key & ~(1ull << r));
+                uint2 ox = table_find(P.xtab, key & ~(1ull << r));
+                return make_uint2(ox.x, ox.y | ((unsigned)r << 24));
             },
             [&](int gT, int gS) -> double {
                 NDet d;
@@ -377,7 +440,7 @@ __device__ double psi_direct(const DevProblem &P, unsigned long long key, unsign
             });
         return P.ccls[class_id1(P.V, vcode[0])] * phi;
     }
-    return P.ccls[class_id2(P.V, vcode[0], vcode[1])] * phi2(P, vcode[0], vcode[1], table_find(P.xtab, key));
+    return P.ccls[class_id2(P.V, vcode[0], vcode[1])] * phi2<false>(P, vcode[0], vcode[1], table_find(P.xtab, key));
 }
 
 // Row r of a block, independent of the group: the virtual set of m, its
@@ -454,12 +517,55 @@ struct RowRes {
     bool ok;
 };
 
+// A group as one lane sees it.  U: the same group for the whole wave, its
+// fields held in scalar registers and its lists read with scalar loads.
+struct GroupView {
+    unsigned long long xkey;
+    double phi;
+    int rg0, rg1, pg0, pg1, nl;
+    const uint2 *lst;
+};
+
+template <bool U>
+__device__ __forceinline__ GroupView group_view(const WaveLDS &L, unsigned gi) {
+    const GroupInfo &G = L.G[gi];
+    GroupView v;
+    v.xkey = G.xkey;
+    v.phi = G.phi;
+    v.rg0 = G.rg[0];
+    v.rg1 = G.rg[1];
+    v.pg0 = G.pg[0];
+    v.pg1 = G.pg[1];
+    v.nl = G.nl;
+    if (U) {
+        v.xkey = uni(v.xkey);
+        v.phi = uni(v.phi);
+        v.rg0 = uni(v.rg0);
+        v.rg1 = uni(v.rg1);
+        v.pg0 = uni(v.pg0);
+        v.pg1 = uni(v.pg1);
+        v.nl = uni(v.nl);
+    }
+    v.lst = L.lst + gi * L.NL;
+    return v;
+}
+
+template <bool U>
+__device__ __forceinline__ uint2 view_list(const GroupView &v, int k) {
+    uint2 o = v.lst[k];
+    if (U) {
+        o.x = uni(o.x);
+        o.y = uni(o.y);
+    }
+    return o;
+}
+
 // row d of group G: <m|H|n>, psi(m), the Dyall element if m keeps n's virtual set
-template <int VP>
+template <int VP, bool U>
 __device__ __forceinline__ void row_eval(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L,
-                                         const RowDec &d, const GroupInfo &G, const uint2 *lst, RowRes &o) {
+                                         const RowDec &d, const GroupView &G, RowRes &o) {
     // outer excitation n -> m: removed P*, added Q* (ascending spin-orbital order)
-    int Pr0 = G.rg[0], Pr1 = G.rg[1], Qa0 = G.pg[0], Qa1 = G.pg[1];
+    int Pr0 = G.rg0, Pr1 = G.rg1, Qa0 = G.pg0, Qa1 = G.pg1;
     if (Pr0 < 0) { Pr0 = d.rv0; Pr1 = d.rv1; } else if (Pr1 < 0) Pr1 = d.rv0;
     if (Qa0 < 0) { Qa0 = d.ad0; Qa1 = d.ad1; } else if (Qa1 < 0) Qa1 = d.ad0;
     if (Pr1 >= 0 && Pr0 > Pr1) { int t = Pr0; Pr0 = Pr1; Pr1 = t; }
@@ -483,19 +589,20 @@ __device__ __forceinline__ void row_eval(const DevProblem &P, const WalkerCtx &W
     if (VP == 0) {
         phi = G.phi;
     } else if (VP == 1) {
-        phi = phi1(P, G.xkey, d.Lp0, [&](int k) -> uint2 { return lst[k]; },
-                   [&](int gT, int gS) -> double { return fock_y(P, W, L, G, gT, gS); });
+        phi = phi1<U>(P, G.xkey, d.Lp0, G.nl, [&](int k) -> uint2 { return view_list<U>(G, k); },
+                      [&](int gT, int gS) -> double { return fock_y(P, W, L, G.rg0, G.rg1, G.pg0, G.pg1, gT, gS); });
     } else {
-        phi = phi2(P, d.Lp0, d.Lp1, lst[0]);
+        phi = phi2<U>(P, d.Lp0, d.Lp1, view_list<U>(G, 0));
     }
     o.psi = d.c * phi;
 }
 
+template <bool U>
 __device__ __forceinline__ void row_eval_any(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, int vp,
-                                             const RowDec &d, const GroupInfo &G, const uint2 *lst, RowRes &o) {
-    if (vp == 0) row_eval<0>(P, W, L, d, G, lst, o);
-    else if (vp == 1) row_eval<1>(P, W, L, d, G, lst, o);
-    else row_eval<2>(P, W, L, d, G, lst, o);
+                                             const RowDec &d, const GroupView &G, RowRes &o) {
+    if (vp == 0) row_eval<0, U>(P, W, L, d, G, o);
+    else if (vp == 1) row_eval<1, U>(P, W, L, d, G, o);
+    else row_eval<2, U>(P, W, L, d, G, o);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -600,19 +707,55 @@ __device__ void sweep_block(const DevProblem &P, const WalkerCtx &W, const WaveL
     if (ntile == 1 && sub < b.R) row_decode(P, W, b, sub, d);
     for (long long gb = 0; gb < b.ng; gb += WAVE) {
         long long g = gb + lane;
-        unsigned ngc = (unsigned)min((long long)WAVE, b.ng - gb);
-        if (g < b.ng) group_setup(P, W, L, b, g, mg, mlst);
+        bool live = false;
+        if (g < b.ng) {
+            group_setup(P, W, L, b, g, mg, mlst);
+            live = mg.live;
+        }
+        // rows of a group whose lookups all came back empty have psi(m) = 0:
+        // they add nothing to E_L, E_D,L or the rates, so only live groups are swept
+        unsigned long long lm = __ballot(live);
+        unsigned nlive = (unsigned)__popcll(lm);
+        if (live) L.perm[__popcll(lm & ((1ull << lane) - 1ull))] = (unsigned char)lane;
         __syncwarp();
+        if (S == WAVE) {
+            // one group per pass: its data is wave-uniform
+            for (unsigned t = 0; t < ntile; t++) {
+                unsigned r = t * WAVE + sub;
+                bool rv = r < b.R;
+                if (ntile > 1 && rv) row_decode(P, W, b, r, d);
+                for (unsigned gc = 0; gc < nlive; gc++) {
+                    unsigned gi = uni((unsigned)L.perm[gc]);
+                    GroupView gv = group_view<true>(L, gi);
+                    double v = 0.0;
+                    if (rv) {
+                        RowRes o;
+                        row_eval_any<true>(P, W, L, vp, d, gv, o);
+                        if (o.ok) {
+                            a.E += o.hnm * o.psi;
+                            v = fabs(o.psi);
+                            a.G += v;
+                            if (dy && d.same) a.D += o.hd * o.psi;
+                        }
+                    }
+                    v = wave_sum(v);
+                    if (lane == 0) L.G[gi].gam += v;
+                    __syncwarp();
+                }
+            }
+        } else
         for (unsigned t = 0; t < ntile; t++) {
             unsigned r = t * S + sub;
             bool rv = r < b.R;
             if (ntile > 1 && rv) row_decode(P, W, b, r, d);
-            for (unsigned gp = 0; gp < ngc; gp += gpi) {
-                unsigned gi = gp + grp;
+            for (unsigned gp = 0; gp < nlive; gp += gpi) {
+                unsigned gc = gp + grp;
+                unsigned gi = gc < nlive ? L.perm[gc] : 0u;
                 double v = 0.0;
-                if (rv && gi < ngc) {
+                if (rv && gc < nlive) {
                     RowRes o;
-                    row_eval_any(P, W, L, vp, d, L.G[gi], L.lst + gi * L.NL, o);
+                    GroupView gv = group_view<false>(L, gi);
+                    row_eval_any<false>(P, W, L, vp, d, gv, o);
                     if (o.ok) {
                         a.E += o.hnm * o.psi;
                         v = fabs(o.psi);
@@ -621,7 +764,7 @@ __device__ void sweep_block(const DevProblem &P, const WalkerCtx &W, const WaveL
                     }
                 }
                 v = subwave_sum(v, S);
-                if (sub == 0 && gi < ngc) L.G[gi].gam += v;
+                if (sub == 0 && gc < nlive) L.G[gi].gam += v;
                 __syncwarp();
             }
         }
@@ -689,6 +832,7 @@ __device__ void walker_eval(const DevProblem &P, const WaveLDS &L, int lane, uns
     uint2 *slst = L.lst + WAVE * L.NL;
     if (lane == 0) group_setup(P, W, L, b, a.bestg, sg, slst);
     __syncwarp();
+    GroupView sgv = group_view<true>(L, WAVE);
     int vp = b.vp[0] + b.vp[1];
     double b2 = INFINITY;
     int bcls = 0x7fffffff;
@@ -698,7 +842,7 @@ __device__ void walker_eval(const DevProblem &P, const WaveLDS &L, int lane, uns
         RowDec d;
         row_decode(P, W, b, r, d);
         RowRes o;
-        row_eval_any(P, W, L, vp, d, sg, slst, o);
+        row_eval_any<true>(P, W, L, vp, d, sgv, o);
         if (!o.ok || o.psi == 0.0) continue;
         double tau = exp_draw(P.seed, wid, step, 1u, (uint32_t)d.cls, 0u) / fabs(o.psi);
         if (tau < b2 || (tau == b2 && d.cls < bcls)) {
@@ -884,7 +1028,8 @@ __global__ __launch_bounds__(64) void k_neighbors(DevProblem P, unsigned long lo
                         RowDec d;
                         row_decode(P, W, b, r, d);
                         RowRes o;
-                        row_eval_any(P, W, L, vp, d, mg, mlst, o);
+                        GroupView gv = group_view<false>(L, lane);
+                        row_eval_any<false>(P, W, L, vp, d, gv, o);
                         if (!o.ok) continue;
                         unsigned long long pos = atomicAdd(count, 1ull);
                         if ((long long)pos < cap) {
