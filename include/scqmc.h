@@ -79,13 +79,15 @@ typedef struct {
 } scqmc_options;
 
 typedef struct {
-    double e_var, e_var_err;    /* eq:vmc: sum t E_L / sum t, delete-one jackknife over walkers */
+    double e_var, e_var_err;    /* eq:vmc: sum t E_L / sum t; delete-one jackknife over min(W, 256)
+                                   groups of consecutive walkers */
     double a0_sq, a0_sq_err;    /* CAS residence fraction (Davidson section) */
     double e_ref;               /* E_0^(0) as given to set_dyall (0 if not given) */
     double davidson;            /* (1 - a0^2)(e_var - e_ref), Davidson correction equation */
-    double e2, e2_err;          /* SC-NEVPT2 E^(2) (eq:nevpt2e2) from the sampled sums; error
-                                   from the jackknife over walker groups is not available
-                                   per class, e2_err is NaN */
+    double e2, e2_err;          /* SC-NEVPT2 E^(2) (eq:nevpt2e2) from the sampled class sums;
+                                   error: delete-one jackknife over min(W, 16) groups of
+                                   consecutive walkers, each with its own class sums (NaN
+                                   when W = 1 or a leave-one-out estimate is undefined) */
     int64_t n_steps_accumulated, n_walkers;
 } scqmc_estimates;
 

@@ -68,6 +68,7 @@ struct scqmc_ctx {
     std::vector<double> ccls_h, eps_h;
     // walkers
     long long W = 0, step = 0;
+    long long ncg = 0;   // walker groups with their own class sums (jackknife of E^(2))
     unsigned long long seed = 0;
     DBuf wkey, wvirt, wpsi, wsum, cacc, bad;
     // snapshot scratch
@@ -133,6 +134,11 @@ static DevProblem dev_problem(const scqmc_ctx *c) {
 }
 
 static int lists_per_group(const scqmc_ctx *c) { return std::max(1, c->nea + c->neb); }
+
+// Class sums are kept per group of consecutive walkers (group of walker w:
+// w * ncg / W), so that E^(2) gets a jackknife error like E_var.
+static long long class_groups(long long W) { return std::min<long long>(W, 16); }
+static size_t class_acc_bytes(const scqmc_ctx *c) { return (size_t)64 * c->ncg * c->ncls; }
 
 // Host compaction of one full determinant: active key, packed virtual codes.
 // Returns false (with a reason) if it is outside the allowed space.
@@ -495,12 +501,13 @@ scqmc_status scqmc_init_walkers(scqmc_ctx *c, int64_t W, const uint64_t *dets, u
     TRY(dalloc(c, c->wvirt, sizeof(unsigned) * W));
     TRY(dalloc(c, c->wpsi, sizeof(double) * W));
     TRY(dalloc(c, c->wsum, sizeof(double) * 3 * W));
-    TRY(dalloc(c, c->cacc, sizeof(unsigned long long) * 8 * c->ncls));
+    c->ncg = class_groups(W);
+    TRY(dalloc(c, c->cacc, class_acc_bytes(c)));
     TRY(dalloc(c, c->bad, sizeof(unsigned long long)));
     HIPCHK(c, hipMemcpyAsync(c->wkey.p, keys.data(), sizeof(unsigned long long) * W, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->wvirt.p, virts.data(), sizeof(unsigned) * W, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemsetAsync(c->wsum.p, 0, sizeof(double) * 3 * W, c->stream));
-    HIPCHK(c, hipMemsetAsync(c->cacc.p, 0, sizeof(unsigned long long) * 8 * c->ncls, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->cacc.p, 0, class_acc_bytes(c), c->stream));
     HIPCHK(c, hipMemsetAsync(c->bad.p, 0, sizeof(unsigned long long), c->stream));
     c->seed = seed;
     DevProblem P = dev_problem(c);
@@ -534,6 +541,7 @@ scqmc_status scqmc_sample(scqmc_ctx *c, int64_t n_steps) {
     S.psi = c->wpsi.as<double>();
     S.wsum = c->wsum.as<double>();
     S.cacc = c->cacc.as<unsigned long long>();
+    S.ncg = (int)c->ncg;
     S.bad = c->bad.as<unsigned long long>();
     int NL = lists_per_group(c);
     size_t lds = kernel_lds(c);
@@ -555,28 +563,55 @@ scqmc_status scqmc_synchronize(scqmc_ctx *c) {
     return SCQMC_OK;
 }
 
-static scqmc_status download_sums(scqmc_ctx *c, std::vector<double> &ws, std::vector<double> &cs) {
+static double fixed_to_double(unsigned long long lo, unsigned long long hi) {
+    return (double)(long long)hi + std::ldexp((double)lo, -64);
+}
+
+// ws: per-walker sums [3][W]; cs: class sums over all walkers [4][ncls] (exact
+// 128-bit totals, then rounded); gs (optional): per walker group [ncg][4][ncls]
+static scqmc_status download_sums(scqmc_ctx *c, std::vector<double> &ws, std::vector<double> &cs,
+                                  std::vector<double> *gs = nullptr) {
     ws.resize(3 * c->W);
-    std::vector<unsigned long long> acc(8 * c->ncls);
+    long long n4 = 4 * c->ncls;
+    std::vector<unsigned long long> acc(2 * n4 * c->ncg);
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, hipMemcpyAsync(ws.data(), c->wsum.p, sizeof(double) * 3 * c->W, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(acc.data(), c->cacc.p, sizeof(unsigned long long) * 8 * c->ncls, hipMemcpyDeviceToHost,
-                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(acc.data(), c->cacc.p, class_acc_bytes(c), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    cs.resize(4 * c->ncls);
-    for (long long i = 0; i < 4 * c->ncls; i++) {
-        unsigned long long lo = acc[2 * i];
-        long long hi = (long long)acc[2 * i + 1];
-        cs[i] = (double)hi + std::ldexp((double)lo, -64);
+    cs.resize(n4);
+    if (gs) gs->resize(n4 * c->ncg);
+    for (long long i = 0; i < n4; i++) {
+        unsigned long long lo = 0, hi = 0;
+        for (long long g = 0; g < c->ncg; g++) {
+            unsigned long long l = acc[2 * (g * n4 + i)], h = acc[2 * (g * n4 + i) + 1];
+            unsigned long long nl = lo + l;
+            hi += h + (nl < lo ? 1ull : 0ull);
+            lo = nl;
+            if (gs) (*gs)[g * n4 + i] = fixed_to_double(l, h);
+        }
+        cs[i] = fixed_to_double(lo, hi);
     }
     return SCQMC_OK;
+}
+
+// E^(2) of eq:nevpt2e2 from class sums N_l = sum t/c_l^2, D_l = sum t E_D,L/c_l^2
+static double e2_from_sums(const double *nl_, const double *dl_, long long n, double e0) {
+    double n0 = nl_[0];
+    if (!(n0 > 0)) return NAN;
+    double e2 = 0;
+    for (long long l = 1; l < n; l++) {
+        double nl = nl_[l];
+        if (nl <= 0) continue;
+        e2 += (nl / n0) / (e0 - dl_[l] / nl);
+    }
+    return e2;
 }
 
 scqmc_status scqmc_read_estimates(scqmc_ctx *c, scqmc_estimates *out) {
     if (!c || !out) return SCQMC_E_INVALID_ARG;
     if (!c->has_walkers) FAIL(c, SCQMC_E_STATE, "init_walkers first");
-    std::vector<double> ws, cs;
-    TRY(download_sums(c, ws, cs));
+    std::vector<double> ws, cs, gsum;
+    TRY(download_sums(c, ws, cs, &gsum));
     long long W = c->W;
     // delete-one jackknife over groups of consecutive walkers
     long long G = std::min<long long>(W, 256);
@@ -618,17 +653,29 @@ scqmc_status scqmc_read_estimates(scqmc_ctx *c, scqmc_estimates *out) {
     out->e2 = NAN;
     out->e2_err = NAN;
     if (c->opt.mode == 1 && c->has_dyall) {
-        long long n = c->ncls;
-        double n0 = cs[2 * n + 0];
-        if (n0 > 0) {
-            double e2 = 0;
-            for (long long l = 1; l < n; l++) {
-                double nl = cs[2 * n + l];
-                if (nl <= 0) continue;
-                double el = cs[3 * n + l] / nl;
-                e2 += (nl / n0) / (c->e0_ref - el);
+        long long n = c->ncls, K = c->ncg;
+        out->e2 = e2_from_sums(&cs[2 * n], &cs[3 * n], n, c->e0_ref);
+        // delete-one jackknife over the walker groups of the class sums
+        if (K > 1 && std::isfinite(out->e2)) {
+            std::vector<double> nl(n), dl(n), je(K);
+            double m = 0;
+            bool ok = true;
+            for (long long g = 0; g < K; g++) {
+                const double *gp = &gsum[g * 4 * n];
+                for (long long l = 0; l < n; l++) {
+                    nl[l] = cs[2 * n + l] - gp[2 * n + l];
+                    dl[l] = cs[3 * n + l] - gp[3 * n + l];
+                }
+                je[g] = e2_from_sums(nl.data(), dl.data(), n, c->e0_ref);
+                ok = ok && std::isfinite(je[g]);
+                m += je[g];
             }
-            out->e2 = e2;
+            if (ok) {
+                m /= K;
+                double v = 0;
+                for (long long g = 0; g < K; g++) v += (je[g] - m) * (je[g] - m);
+                out->e2_err = std::sqrt((K - 1.0) / K * v);
+            }
         }
     }
     return SCQMC_OK;
@@ -769,12 +816,12 @@ scqmc_status scqmc_debug_neighbors(scqmc_ctx *c, const uint64_t *det, int64_t ca
 }
 
 // checkpoint layout: header of 12 int64, then key[W] u64, virt[W] u32 (padded to 8),
-// psi[W], wsum[3W], cacc[8 ncls] u64, bad u64
+// psi[W], wsum[3W], class sums [ncg][4][ncls] x 2 u64 (ncg = min(W, 16)), bad u64
 static const int64_t kMagic = 0x31435153514d4353LL;
 
 static int64_t state_bytes(const scqmc_ctx *c) {
     int64_t W = c->W;
-    return 12 * 8 + 8 * W + ((4 * W + 7) / 8) * 8 + 8 * W + 24 * W + 64 * c->ncls + 8;
+    return 12 * 8 + 8 * W + ((4 * W + 7) / 8) * 8 + 8 * W + 24 * W + 64 * class_groups(W) * c->ncls + 8;
 }
 
 scqmc_status scqmc_save_state(scqmc_ctx *c, void *buf, int64_t cap, int64_t *used) {
@@ -785,7 +832,7 @@ scqmc_status scqmc_save_state(scqmc_ctx *c, void *buf, int64_t cap, int64_t *use
     if (!buf || cap < need) FAIL(c, SCQMC_E_INVALID_ARG, "buffer too small");
     char *b = (char *)buf;
     std::memset(b, 0, need);
-    int64_t hdr[12] = {kMagic, 1, c->W, c->ncls, c->N, c->C, c->A, c->na, c->nb, c->step, (int64_t)c->seed, c->n_ref};
+    int64_t hdr[12] = {kMagic, 2, c->W, c->ncls, c->N, c->C, c->A, c->na, c->nb, c->step, (int64_t)c->seed, c->n_ref};
     std::memcpy(b, hdr, sizeof(hdr));
     int64_t W = c->W, o = 96;
     HIPCHK(c, hipSetDevice(c->device));
@@ -794,7 +841,7 @@ scqmc_status scqmc_save_state(scqmc_ctx *c, void *buf, int64_t cap, int64_t *use
     HIPCHK(c, hipMemcpy(b + o, c->wvirt.p, 4 * W, hipMemcpyDeviceToHost)); o += ((4 * W + 7) / 8) * 8;
     HIPCHK(c, hipMemcpy(b + o, c->wpsi.p, 8 * W, hipMemcpyDeviceToHost)); o += 8 * W;
     HIPCHK(c, hipMemcpy(b + o, c->wsum.p, 24 * W, hipMemcpyDeviceToHost)); o += 24 * W;
-    HIPCHK(c, hipMemcpy(b + o, c->cacc.p, 64 * c->ncls, hipMemcpyDeviceToHost)); o += 64 * c->ncls;
+    HIPCHK(c, hipMemcpy(b + o, c->cacc.p, class_acc_bytes(c), hipMemcpyDeviceToHost)); o += class_acc_bytes(c);
     HIPCHK(c, hipMemcpy(b + o, c->bad.p, 8, hipMemcpyDeviceToHost));
     return SCQMC_OK;
 }
@@ -805,13 +852,14 @@ scqmc_status scqmc_load_state(scqmc_ctx *c, const void *buf, int64_t len) {
     if (len < 96) FAIL(c, SCQMC_E_INVALID_ARG, "state buffer too short");
     int64_t hdr[12];
     std::memcpy(hdr, buf, sizeof(hdr));
-    if (hdr[0] != kMagic || hdr[1] != 1) FAIL(c, SCQMC_E_INVALID_ARG, "not a checkpoint");
+    if (hdr[0] != kMagic || hdr[1] != 2) FAIL(c, SCQMC_E_INVALID_ARG, "not a checkpoint of this format");
     if (hdr[3] != c->ncls || hdr[4] != c->N || hdr[5] != c->C || hdr[6] != c->A || hdr[7] != c->na ||
         hdr[8] != c->nb || hdr[11] != c->n_ref)
         FAIL(c, SCQMC_E_INVALID_ARG, "checkpoint from a different problem");
     int64_t W = hdr[2];
     if (W <= 0 || W >= (1LL << 31)) FAIL(c, SCQMC_E_INVALID_ARG, "bad walker count in checkpoint");
     c->W = W;
+    c->ncg = class_groups(W);
     if (len < state_bytes(c)) FAIL(c, SCQMC_E_INVALID_ARG, "state buffer too short");
     const char *b = (const char *)buf;
     HIPCHK(c, hipSetDevice(c->device));
@@ -819,14 +867,14 @@ scqmc_status scqmc_load_state(scqmc_ctx *c, const void *buf, int64_t len) {
     TRY(dalloc(c, c->wvirt, 4 * W));
     TRY(dalloc(c, c->wpsi, 8 * W));
     TRY(dalloc(c, c->wsum, 24 * W));
-    TRY(dalloc(c, c->cacc, 64 * c->ncls));
+    TRY(dalloc(c, c->cacc, class_acc_bytes(c)));
     TRY(dalloc(c, c->bad, 8));
     int64_t o = 96;
     HIPCHK(c, hipMemcpy(c->wkey.p, b + o, 8 * W, hipMemcpyHostToDevice)); o += 8 * W;
     HIPCHK(c, hipMemcpy(c->wvirt.p, b + o, 4 * W, hipMemcpyHostToDevice)); o += ((4 * W + 7) / 8) * 8;
     HIPCHK(c, hipMemcpy(c->wpsi.p, b + o, 8 * W, hipMemcpyHostToDevice)); o += 8 * W;
     HIPCHK(c, hipMemcpy(c->wsum.p, b + o, 24 * W, hipMemcpyHostToDevice)); o += 24 * W;
-    HIPCHK(c, hipMemcpy(c->cacc.p, b + o, 64 * c->ncls, hipMemcpyHostToDevice)); o += 64 * c->ncls;
+    HIPCHK(c, hipMemcpy(c->cacc.p, b + o, class_acc_bytes(c), hipMemcpyHostToDevice)); o += class_acc_bytes(c);
     HIPCHK(c, hipMemcpy(c->bad.p, b + o, 8, hipMemcpyHostToDevice));
     c->step = hdr[9];
     c->seed = (unsigned long long)hdr[10];

@@ -906,8 +906,9 @@ struct WalkerArrays {
     unsigned *virt;
     double *psi;
     double *wsum;                 // [3][W]
-    unsigned long long *cacc;     // [4][ncls][2]
+    unsigned long long *cacc;     // [ncg][4][ncls][2]
     unsigned long long *bad;      // [1]
+    int ncg;                      // walker groups of the class sums
 };
 
 __device__ __forceinline__ long long class_of_virt(const DevProblem &P, unsigned virt) {
@@ -948,7 +949,8 @@ __global__ __launch_bounds__(256, 4) void k_sample(DevProblem P, WalkerArrays S,
                 double c = P.ccls[cls];
                 double q = lane == 0 ? t : lane == 1 ? t * o.eloc : lane == 2 ? t / (c * c)
                                                                   : ((P.mode == 1 && cls != 0) ? t * o.elocd / (c * c) : 0.0);
-                fx_add(S.cacc + ((long long)lane * P.ncls + cls) * 2, q);
+                long long grp = w * S.ncg / W;
+                fx_add(S.cacc + ((grp * 4 + lane) * P.ncls + cls) * 2, q);
             }
         }
         key = o.key_new;

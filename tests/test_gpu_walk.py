@@ -1,0 +1,160 @@
+"""GPU walk: statistics against exact values, checkpoint / resume, batch
+invariance and the error paths of the C ABI.
+
+The statistical test runs the HIP walk of the 12-orbital system and checks
+the estimators of eq:vmc (E_var), the Davidson section (a0^2) and
+eq:nevpt2e2 (E^(2)) against the brute-force values within their own
+jackknife errors.  The other tests check properties that hold exactly.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import brute
+from helpers import cfg1_problem, tiny_problem, TINY
+from paper_1909_06935_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _engine(prob, **kw):
+    from paper_1909_06935_amd.scqmc import Engine
+    return Engine.from_problem(prob, **kw)
+
+
+def test_statistics_cfg1_against_exact():
+    prob = cfg1_problem()
+    _say("cfg1 statistics")
+    b = brute.Brute(prob, wl.dense_eri(prob.chol), eps_virt=prob.eps_virt)
+    eng = _engine(prob, mode=1, burn_in=100, block_len=50)
+    w0 = wl.draw_walkers(prob.ref_dets, prob.ref_coeff, 256, prob.seed_walk)
+    eng.init_walkers(w0, prob.seed_walk)
+    eng.sample(1100)
+    est = eng.read_estimates()
+    steps, bad = eng.read_counters()
+    assert steps == 1100 and bad == 0
+    assert est["n_steps_accumulated"] == 1000
+    assert est["e_var_err"] > 0 and est["a0_sq_err"] > 0 and est["e2_err"] > 0
+    assert abs(est["e_var"] - b.e_var) < 5 * est["e_var_err"], (est, b.e_var)
+    assert abs(est["a0_sq"] - b.a0_sq) < 5 * est["a0_sq_err"], (est, b.a0_sq)
+    # E^(2) is a ratio of sampled sums: 6 sigma covers its small bias as well
+    assert abs(est["e2"] - b.e2) < 6 * est["e2_err"], (est, b.e2)
+    assert abs(est["davidson"] - (1 - est["a0_sq"]) * (est["e_var"] - prob.e0_ref)) < 1e-12
+
+
+def _state(eng):
+    d, psi = eng.read_walkers()
+    return d, psi, eng.read_walker_sums(), eng.read_class_sums(), eng.read_counters()
+
+
+def _same_state(a, b, n=None):
+    sl = slice(None) if n is None else slice(0, n)
+    assert np.array_equal(a[0][sl], b[0][sl])
+    assert np.array_equal(a[1][sl], b[1][sl])
+    assert np.array_equal(a[2][sl], b[2][sl])
+
+
+def test_checkpoint_resume_bit_exact():
+    prob = cfg1_problem()
+    _say("checkpoint")
+    w0 = wl.draw_walkers(prob.ref_dets, prob.ref_coeff, 96, prob.seed_walk)
+    e1 = _engine(prob, mode=1, burn_in=3, block_len=4)
+    e1.init_walkers(w0, prob.seed_walk)
+    e1.sample(10)
+    blob = e1.save_state()
+    e1.sample(12)
+    ref = _state(e1)
+    e2 = _engine(prob, mode=1, burn_in=3, block_len=4)
+    e2.load_state(blob)
+    e2.sample(12)
+    got = _state(e2)
+    _same_state(ref, got)
+    for k in ("n", "d", "t", "te"):
+        assert np.array_equal(ref[3][k], got[3][k]), k
+    assert ref[4] == got[4]
+    assert e1.read_estimates() == e2.read_estimates()
+
+
+def test_batch_invariance():
+    """A walker's chain depends on its id, the seed and its start only: the
+    first 40 walkers of a 96-walker run walk exactly as a 40-walker run."""
+    prob = cfg1_problem()
+    _say("batch invariance")
+    w0 = wl.draw_walkers(prob.ref_dets, prob.ref_coeff, 96, prob.seed_walk)
+    big = _engine(prob, mode=1, burn_in=2, block_len=5)
+    big.init_walkers(w0, prob.seed_walk)
+    big.sample(25)
+    small = _engine(prob, mode=1, burn_in=2, block_len=3)
+    small.init_walkers(w0[:40], prob.seed_walk)
+    small.sample(25)
+    _same_state(_state(big), _state(small), n=40)
+
+
+def test_deterministic_repeat():
+    """Two runs of the same walk give bit-identical class sums (fixed-point
+    accumulation does not depend on the order of the atomics)."""
+    prob = cfg1_problem()
+    out = []
+    for _ in range(2):
+        e = _engine(prob, mode=1, burn_in=0, block_len=8)
+        e.init_walkers(wl.draw_walkers(prob.ref_dets, prob.ref_coeff, 256, prob.seed_walk), prob.seed_walk)
+        e.sample(16)
+        out.append(e.read_class_sums())
+    for k in out[0]:
+        assert np.array_equal(out[0][k], out[1][k]), k
+
+
+def test_error_paths():
+    from paper_1909_06935_amd.scqmc import Engine, ScqmcError, E_INVALID_ARG, E_STATE
+    prob = tiny_problem(TINY[0])
+    sp = prob.space
+
+    def status_of(fn):
+        with pytest.raises(ScqmcError) as ei:
+            fn()
+        return ei.value.status
+
+    e = Engine()
+    # call order
+    assert status_of(lambda: e.set_reference(prob.ref_dets, prob.ref_coeff)) == E_STATE
+    assert status_of(lambda: e.sample(1)) == E_STATE
+    e.set_space(sp)
+    e.set_integrals_chol(prob.h1, prob.chol, prob.e_const)
+    # a reference determinant with a virtual electron
+    bad = prob.ref_dets.copy()
+    oa, ob = wl.unpack_det(sp, bad[0])
+    oa = list(oa)
+    oa[-1] = sp.n_orb - 1
+    bad[0] = wl.pack_det(sp, oa, ob)
+    assert status_of(lambda: e.set_reference(bad, prob.ref_coeff)) == E_INVALID_ARG
+    # duplicate reference determinants
+    dup = np.concatenate([prob.ref_dets, prob.ref_dets[:1]])
+    assert status_of(lambda: e.set_reference(dup, np.ones(len(dup)))) == E_INVALID_ARG
+    e.set_reference(prob.ref_dets, prob.ref_coeff)
+    # wrong number of class coefficients
+    assert status_of(lambda: e.set_sc_coeffs(1.0, np.ones(sp.n_classes))) == E_INVALID_ARG
+    e.set_sc_coeffs(prob.c0, prob.c_cls)
+    e.set_options(mode=0)
+    # a walker outside the allowed space: a hole in the core
+    assert sp.n_core > 0
+    w = prob.ref_dets[:1].copy()
+    oa, ob = wl.unpack_det(sp, w[0])
+    free = [p for p in range(sp.n_core, sp.n_core + sp.n_act) if p not in oa]
+    w[0] = wl.pack_det(sp, sorted([p for p in oa if p != 0] + free[:1]), ob)
+    assert status_of(lambda: e.init_walkers(w, 1)) == E_INVALID_ARG
+    assert status_of(lambda: e.init_walkers(prob.ref_dets[:0], 1)) == E_INVALID_ARG
+    e.init_walkers(prob.ref_dets[:4], 1)
+    e.sample(2)
+    # a checkpoint of another problem is refused
+    other = tiny_problem(TINY[1])
+    e2 = Engine.from_problem(other)
+    e2.init_walkers(other.ref_dets[:2], 1)
+    blob = e2.save_state()
+    assert status_of(lambda: e.load_state(blob)) == E_INVALID_ARG
+    assert status_of(lambda: e.load_state(blob[:50])) == E_INVALID_ARG
