@@ -160,6 +160,9 @@ def main():
     W = args.walkers or wl.CONFIGS[args.config]["walkers"]
     stream = torch.cuda.Stream()
     eng = Engine.from_problem(prob, mode=1, burn_in=args.warmup, block_len=args.block, stream=stream)
+    if prob.e0_ref == 0.0:
+        # no stored CAS energy for this workload: E_0^(0) of its reference, on the device
+        eng.set_dyall(prob.eps_virt, eng.reference_energy())
     w0 = wl.draw_walkers(prob.ref_dets, prob.ref_coeff, W, prob.seed_walk)
     eng.init_walkers(w0, prob.seed_walk)
     print(f"# {args.config}: {W} walkers, warmup {args.warmup} steps", file=sys.stderr, flush=True)

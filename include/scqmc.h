@@ -133,6 +133,34 @@ scqmc_status scqmc_set_sc_coeffs(scqmc_ctx *ctx, double c0, const double *c_cls,
  * included, so <phi0|H_D|phi0> = <phi0|H|phi0>).  Required for mode 1. */
 scqmc_status scqmc_set_dyall(scqmc_ctx *ctx, const double *eps_virt, double e0_ref);
 
+/* E_0^(0) = <phi0|H|phi0> / <phi0|phi0>, the zeroth-order energy of
+ * "SC-NEVPT2(s)", evaluated on the device (the local energy of every reference
+ * determinant over its active-space neighbours, summed on the host with
+ * weights phi0(d)^2 in reference order).  Needs set_reference; writes *e0.
+ * SCQMC_E_NUMERIC if a local energy is not finite. */
+scqmc_status scqmc_reference_energy(scqmc_ctx *ctx, double *e0);
+
+/* Spin-summed active one-particle density of phi0, normalised:
+ * gamma[t*n_act + u] = sum_sigma <phi0|a+_{t sigma} a_{u sigma}|phi0> / <phi0|phi0>
+ * (t, u active orbitals counted from the first active one).  The density
+ * enters the generalized Fock operator of the Dyall Hamiltonian
+ * ("SC-NEVPT2(s)").  Caller-owned gamma[n_act * n_act].  Needs set_reference. */
+scqmc_status scqmc_reference_rdm1(scqmc_ctx *ctx, double *gamma);
+
+/* Semicanonical virtual orbitals for Dyall's Hamiltonian ("SC-NEVPT2(s)": the
+ * virtual orbital energies come from diagonalising the virtual generalized
+ * Fock operator).  Builds
+ *   F_ab = h_ab + sum_{i core} [2(ab|ii) - (ai|ib)] + sum_{tu} gamma_tu [(ab|tu) - 1/2 (at|ub)]
+ * on the device, diagonalises it on the host (cyclic Jacobi; eigenvalues
+ * ascending, each eigenvector's largest-|component| positive), rotates the
+ * context's integrals to the new virtual orbitals phi'_b = sum_a phi_a U[a][b],
+ * and sets the Dyall Hamiltonian as set_dyall would with eps_virt = the
+ * eigenvalues and e0_ref = E_0^(0).  The reference (active space) is
+ * unchanged; class coefficients refer to the rotated orbitals.  Outputs,
+ * both optional (NULL): eps_virt[V], u[V*V] row-major U[a][b].  Needs
+ * set_reference; invalidates placed walkers (call init_walkers afterwards). */
+scqmc_status scqmc_semicanonicalize(scqmc_ctx *ctx, double *eps_virt, double *u);
+
 scqmc_status scqmc_set_options(scqmc_ctx *ctx, const scqmc_options *opt);
 
 /* Place n_walkers walkers on the given determinants (host [W][2][words]); the

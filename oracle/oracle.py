@@ -67,6 +67,10 @@ def lib():
         L.orc_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
         L.orc_traffic.argtypes = [P, up, C.POINTER(C.c_int64)]
         L.orc_exp_draw.restype = C.c_double
+        L.orc_reference_energy.restype = C.c_double
+        L.orc_reference_energy.argtypes = [P]
+        L.orc_reference_rdm1.restype = None
+        L.orc_reference_rdm1.argtypes = [P, dp]
         L.orc_exp_draw.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]
         _lib = L
     return _lib
@@ -211,6 +215,17 @@ class Oracle:
         lib().orc_traffic(self.h, self._det(det), out)
         return dict(eri=out[0], heff=out[1], ref=out[2], n_nbr=out[3], terms=out[4])
 
+    def reference_energy(self):
+        """E_0^(0) = <phi0|H|phi0>/<phi0|phi0> over all reference pairs."""
+        return float(lib().orc_reference_energy(self.h))
+
+    def reference_rdm1(self):
+        """Spin-summed active one-particle density of phi0, [A, A], normalised."""
+        A = self.space.n_act
+        g = np.zeros(A * A)
+        lib().orc_reference_rdm1(self.h, g)
+        return g.reshape(A, A)
+
     def det_hamiltonian(self, dets):
         """Sparse (COO, upper triangle) Hamiltonian over a determinant list."""
         dets = np.ascontiguousarray(dets, dtype=np.uint64)
@@ -244,3 +259,39 @@ def ground_state(orc: Oracle, dets):
     if x[np.argmax(np.abs(x))] < 0:
         x = -x
     return float(e), x
+
+
+def virtual_fock(space, h1, eri, gamma):
+    """Generalized Fock operator over the virtual orbitals ("SC-NEVPT2(s)":
+    the virtual part of Dyall's Hamiltonian comes from diagonalising it):
+    F_ab = h_ab + sum_{i core} [2(ab|ii) - (ai|ib)] + sum_{tu} gamma_tu [(ab|tu) - 1/2 (at|ub)],
+    gamma the spin-summed normalised active density of phi0."""
+    C, A = space.n_core, space.n_act
+    v = slice(C + A, space.n_orb)
+    act = slice(C, C + A)
+    F = h1[v, v].copy()
+    for i in range(C):
+        F += 2.0 * eri[v, v, i, i] - eri[v, i, i, v]
+    F += np.einsum("tu,abtu->ab", gamma, eri[v, v, act, act])
+    F -= 0.5 * np.einsum("tu,atub->ab", gamma, eri[v, act, act, v])
+    return F
+
+
+def semicanonical(F):
+    """Eigenvalues (ascending) and eigenvectors of F; each eigenvector's
+    largest-|component| is made positive."""
+    w, U = np.linalg.eigh(F)
+    for k in range(U.shape[1]):
+        if U[np.argmax(np.abs(U[:, k])), k] < 0:
+            U[:, k] = -U[:, k]
+    return w, U
+
+
+def rotate_virtuals(space, h1, chol, U):
+    """h1 and Cholesky vectors in the rotated virtual basis phi'_b = sum_a phi_a U[a, b]."""
+    T = np.eye(space.n_orb)
+    v = slice(space.n_core + space.n_act, space.n_orb)
+    T[v, v] = U
+    h = T.T @ h1 @ T
+    B = np.einsum("pi,lpq,qj->lij", T, chol, T)
+    return h, B

@@ -728,6 +728,64 @@ int64_t orc_det_hamiltonian(const orc_t *o, int64_t n, const uint64_t *dets, int
 }
 
 /* ------------------------------------------------------------------ */
+/* properties of the reference phi0 ("SC-NEVPT2(s)": E_0^(0) and the   */
+/* active one-particle density that enters the generalized Fock        */
+/* operator of the semicanonical virtual orbitals)                     */
+/* ------------------------------------------------------------------ */
+/* E_0^(0) = <phi0|H|phi0> / <phi0|phi0>: every pair of reference
+ * determinants through the generic Slater-Condon routine. */
+double orc_reference_energy(const orc_t *o) {
+    int W2 = 2 * o->W;
+    nsum num = {0, 0}, den = {0, 0};
+    for (int64_t i = 0; i < o->n_ref; i++) {
+        const uint64_t *a = o->ref + i * W2;
+        nadd(&den, o->ref_c[i] * o->ref_c[i]);
+        for (int64_t j = 0; j < o->n_ref; j++) {
+            int ph, ne;
+            double h = orc_hmat(o, a, o->ref + j * W2, &ph, &ne);
+            if (ne <= 2 && h != 0.0) nadd(&num, o->ref_c[i] * h * o->ref_c[j]);
+        }
+    }
+    return nval(&num) / nval(&den);
+}
+
+/* Spin-summed active one-particle density of phi0, normalised:
+ * gamma[t*A + u] = sum_sigma <phi0| a+_{t sigma} a_{u sigma} |phi0> / <phi0|phi0>,
+ * t, u active (0..A-1).  The operator is applied to every reference
+ * determinant with its Jordan-Wigner sign and the result looked up. */
+void orc_reference_rdm1(const orc_t *o, double *gamma) {
+    int A = o->A, W2 = 2 * o->W;
+    nsum *acc = (nsum *)calloc((size_t)A * A, sizeof(nsum));
+    nsum den = {0, 0};
+    uint64_t d[2 * MAXW];
+    for (int64_t i = 0; i < o->n_ref; i++) {
+        const uint64_t *b = o->ref + i * W2;
+        double cb = o->ref_c[i];
+        nadd(&den, cb * cb);
+        for (int sg = 0; sg < 2; sg++)
+            for (int u = 0; u < A; u++) {
+                int gu = o->C + u + sg * o->N;
+                if (!bit(o, b, gu)) continue;
+                for (int t = 0; t < A; t++) {
+                    int gt = o->C + t + sg * o->N;
+                    memcpy(d, b, sizeof(uint64_t) * W2);
+                    int sign = (below(o, d, gu) & 1) ? -1 : 1;   /* a_u */
+                    flip(o, d, gu);
+                    if (bit(o, d, gt)) continue;                  /* a+_t on an occupied orbital */
+                    if (below(o, d, gt) & 1) sign = -sign;       /* a+_t */
+                    flip(o, d, gt);
+                    double ca = ref_lookup(o, d);
+                    if (ca != 0.0) nadd(&acc[t * A + u], ca * sign * cb);
+                }
+            }
+    }
+    double n = nval(&den);
+    for (int k = 0; k < A * A; k++) gamma[k] = nval(&acc[k]) / n;
+    free(acc);
+}
+
+
+/* ------------------------------------------------------------------ */
 /* Algorithmic data volume of one walker-step (bench roofline figure)   */
 /* ------------------------------------------------------------------ */
 /* Counts the DISTINCT operands the local-energy sums of one walker-step

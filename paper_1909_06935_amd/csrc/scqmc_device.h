@@ -30,6 +30,7 @@ struct DevProblem {
     int A, V, Np;           // active, virtual, non-core orbital counts
     int nea, neb;           // active-space electrons per spin (n_elec - n_core)
     int mode;               // 0: E_L; 1: + Dyall local energy
+    int active_only;        // 1: only active-space neighbours (reference properties)
     long long ncls;         // number of classes
     double e_core;          // e_const + core energy
     double eps_screen;      // doubles with |<rs||pq>| <= eps are left out (0: keep all)

@@ -17,6 +17,7 @@
 #include "../../include/scqmc.h"
 #include "scqmc_setup.hip"
 #include "scqmc_walk.hip"
+#include "scqmc_refprops.hip"
 
 namespace {
 
@@ -62,7 +63,8 @@ struct scqmc_ctx {
     long long ncls = 0;
     scqmc_options opt{0.0, 0, 0, 0, 0};
     double e_core = 0.0, e0_ref = 0.0;
-    DBuf heff, eri, ccls, eps, refcoef;
+    DBuf heff, eri, ccls, eps, refcoef, refkey;
+    std::vector<double> refcoef_h;
     TableBufs ref, ytab, xtab;
     long long n_ref = 0;
     std::vector<double> ccls_h, eps_h;
@@ -119,6 +121,7 @@ static DevProblem dev_problem(const scqmc_ctx *c) {
     P.nea = c->nea;
     P.neb = c->neb;
     P.mode = c->opt.mode;
+    P.active_only = 0;
     P.ncls = c->ncls;
     P.e_core = c->e_core;
     P.eps_screen = c->opt.eps_screen;
@@ -419,14 +422,17 @@ scqmc_status scqmc_set_reference(scqmc_ctx *c, int64_t n_det, const uint64_t *de
     std::sort(sk.begin(), sk.end());
     if (std::adjacent_find(sk.begin(), sk.end()) != sk.end()) FAIL(c, SCQMC_E_INVALID_ARG, "duplicate reference determinant");
     HIPCHK(c, hipSetDevice(c->device));
-    DBuf rk;
+    DBuf &rk = c->refkey;
     TRY(dalloc(c, rk, sizeof(unsigned long long) * n_det));
     TRY(dalloc(c, c->refcoef, sizeof(double) * n_det));
+    c->refcoef_h.assign(coeff, coeff + n_det);
     HIPCHK(c, hipMemcpyAsync(rk.p, keys.data(), sizeof(unsigned long long) * n_det, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->refcoef.p, coeff, sizeof(double) * n_det, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->refcoef.p, c->refcoef_h.data(), sizeof(double) * n_det, hipMemcpyHostToDevice,
+                             c->stream));
     TRY(build_table(c, 0, rk, n_det, c->ref));
     TRY(build_table(c, 1, rk, n_det, c->ytab));
     TRY(build_table(c, 2, rk, n_det, c->xtab));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     c->n_ref = n_det;
     c->has_ref = true;
     c->has_walkers = false;
@@ -466,6 +472,243 @@ scqmc_status scqmc_set_dyall(scqmc_ctx *c, const double *eps_virt, double e0_ref
     return SCQMC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// reference properties and semicanonical virtual orbitals (Dyall setup)
+// ---------------------------------------------------------------------------
+static double fixed_to_double(unsigned long long lo, unsigned long long hi);
+static size_t kernel_lds(const scqmc_ctx *c) { return WPB * wave_lds_bytes(lists_per_group(c)); }
+
+static double ref_norm2(const scqmc_ctx *c) {
+    double s = 0.0, comp = 0.0;   // Neumaier
+    for (double x : c->refcoef_h) {
+        double v = x * x, t = s + v;
+        comp += std::fabs(s) >= std::fabs(v) ? (s - t) + v : (v - t) + s;
+        s = t;
+    }
+    return s + comp;
+}
+
+static scqmc_status ref_rdm1(scqmc_ctx *c, std::vector<double> &gamma) {
+    int A = c->A;
+    DBuf acc;
+    TRY(dalloc(c, acc, sizeof(unsigned long long) * 2 * A * A));
+    HIPCHK(c, hipMemsetAsync(acc.p, 0, sizeof(unsigned long long) * 2 * A * A, c->stream));
+    DevProblem P = dev_problem(c);
+    hipLaunchKernelGGL(k_ref_rdm1, dim3(grid1(c->n_ref, 64)), dim3(64), 0, c->stream, P,
+                       c->refkey.as<unsigned long long>(), c->refcoef.as<double>(), (long long)c->n_ref,
+                       acc.as<unsigned long long>());
+    HIPCHK(c, hipGetLastError());
+    std::vector<unsigned long long> h(2 * A * A);
+    HIPCHK(c, hipMemcpyAsync(h.data(), acc.p, sizeof(unsigned long long) * 2 * A * A, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double n = ref_norm2(c);
+    gamma.resize(A * A);
+    for (int k = 0; k < A * A; k++) gamma[k] = fixed_to_double(h[2 * k], h[2 * k + 1]) / n;
+    return SCQMC_OK;
+}
+
+static scqmc_status ref_energy(scqmc_ctx *c, double &e0) {
+    long long n = c->n_ref;
+    DBuf virt, valid, eloc, one;
+    TRY(dalloc(c, virt, sizeof(unsigned) * n));
+    TRY(dalloc(c, valid, sizeof(int) * n));
+    TRY(dalloc(c, eloc, sizeof(double) * n));
+    TRY(dalloc(c, one, sizeof(double)));
+    std::vector<unsigned> hv(n, SCQ_NOVIRT | (SCQ_NOVIRT << 16));
+    std::vector<int> hval(n);
+    for (long long i = 0; i < n; i++) hval[i] = c->refcoef_h[i] != 0.0;
+    const double h1 = 1.0;
+    HIPCHK(c, hipMemcpyAsync(virt.p, hv.data(), sizeof(unsigned) * n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(valid.p, hval.data(), sizeof(int) * n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(one.p, &h1, sizeof(double), hipMemcpyHostToDevice, c->stream));
+    // (H phi0)(d) / phi0(d) from the walker kernel over active-space neighbours
+    // only, with the active-space coefficient c0 = 1
+    DevProblem P = dev_problem(c);
+    P.ccls = one.as<double>();
+    P.mode = 0;
+    P.eps_screen = 0.0;
+    P.active_only = 1;
+    int NL = lists_per_group(c);
+    hipLaunchKernelGGL(k_eval, dim3(grid1(n, WPB)), dim3(64 * WPB), kernel_lds(c), c->stream, P,
+                       c->refkey.as<unsigned long long>(), virt.as<unsigned>(), valid.as<int>(), n, NL,
+                       eloc.as<double>(), (double *)nullptr, (double *)nullptr, (double *)nullptr, (int *)nullptr);
+    HIPCHK(c, hipGetLastError());
+    std::vector<double> el(n);
+    HIPCHK(c, hipMemcpyAsync(el.data(), eloc.p, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double s = 0.0, comp = 0.0;
+    for (long long i = 0; i < n; i++) {
+        double x = c->refcoef_h[i];
+        if (x == 0.0) continue;
+        if (!std::isfinite(el[i])) FAIL(c, SCQMC_E_NUMERIC, "non-finite local energy of a reference determinant");
+        double v = x * x * el[i], t = s + v;
+        comp += std::fabs(s) >= std::fabs(v) ? (s - t) + v : (v - t) + s;
+        s = t;
+    }
+    e0 = (s + comp) / ref_norm2(c);
+    return SCQMC_OK;
+}
+
+// Eigen-decomposition of a symmetric matrix by cyclic Jacobi rotations;
+// eigenvalues ascending, each eigenvector's largest-|component| positive.
+static void jacobi_eigh(int n, std::vector<double> a, std::vector<double> &w, std::vector<double> &v) {
+    v.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; i++) v[(size_t)i * n + i] = 1.0;
+    for (int sweep = 0; sweep < 100; sweep++) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < n; i++)
+            for (int j = 0; j < n; j++) {
+                double x = a[(size_t)i * n + j] * a[(size_t)i * n + j];
+                tot += x;
+                if (i != j) off += x;
+            }
+        if (off <= 1e-34 * tot || off == 0.0) break;
+        for (int p = 0; p < n; p++)
+            for (int q = p + 1; q < n; q++) {
+                double apq = a[(size_t)p * n + q];
+                if (apq == 0.0) continue;
+                double app = a[(size_t)p * n + p], aqq = a[(size_t)q * n + q];
+                double theta = (aqq - app) / (2.0 * apq);
+                double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+                for (int k = 0; k < n; k++) {   // A <- A J (columns p, q)
+                    double akp = a[(size_t)k * n + p], akq = a[(size_t)k * n + q];
+                    a[(size_t)k * n + p] = cs * akp - sn * akq;
+                    a[(size_t)k * n + q] = sn * akp + cs * akq;
+                }
+                for (int k = 0; k < n; k++) {   // A <- J^T A (rows p, q)
+                    double apk = a[(size_t)p * n + k], aqk = a[(size_t)q * n + k];
+                    a[(size_t)p * n + k] = cs * apk - sn * aqk;
+                    a[(size_t)q * n + k] = sn * apk + cs * aqk;
+                }
+                for (int k = 0; k < n; k++) {   // V <- V J
+                    double vkp = v[(size_t)k * n + p], vkq = v[(size_t)k * n + q];
+                    v[(size_t)k * n + p] = cs * vkp - sn * vkq;
+                    v[(size_t)k * n + q] = sn * vkp + cs * vkq;
+                }
+            }
+    }
+    std::vector<int> ord(n);
+    for (int i = 0; i < n; i++) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return a[(size_t)x * n + x] < a[(size_t)y * n + y]; });
+    std::vector<double> vs((size_t)n * n);
+    w.resize(n);
+    for (int k = 0; k < n; k++) {
+        int j = ord[k];
+        w[k] = a[(size_t)j * n + j];
+        int imax = 0;
+        for (int i = 1; i < n; i++)
+            if (std::fabs(v[(size_t)i * n + j]) > std::fabs(v[(size_t)imax * n + j])) imax = i;
+        double sg = v[(size_t)imax * n + j] < 0 ? -1.0 : 1.0;
+        for (int i = 0; i < n; i++) vs[(size_t)i * n + k] = sg * v[(size_t)i * n + j];
+    }
+    v.swap(vs);
+}
+
+scqmc_status scqmc_reference_energy(scqmc_ctx *c, double *e0) {
+    if (!c || !e0) return SCQMC_E_INVALID_ARG;
+    if (!c->has_ref) FAIL(c, SCQMC_E_STATE, "set_reference first");
+    HIPCHK(c, hipSetDevice(c->device));
+    return ref_energy(c, *e0);
+}
+
+scqmc_status scqmc_reference_rdm1(scqmc_ctx *c, double *gamma) {
+    if (!c || !gamma) return SCQMC_E_INVALID_ARG;
+    if (!c->has_ref) FAIL(c, SCQMC_E_STATE, "set_reference first");
+    HIPCHK(c, hipSetDevice(c->device));
+    std::vector<double> g;
+    TRY(ref_rdm1(c, g));
+    std::memcpy(gamma, g.data(), sizeof(double) * g.size());
+    return SCQMC_OK;
+}
+
+scqmc_status scqmc_semicanonicalize(scqmc_ctx *c, double *eps_virt, double *u_out) {
+    if (!c) return SCQMC_E_INVALID_ARG;
+    if (!c->has_ref) FAIL(c, SCQMC_E_STATE, "set_reference first");
+    HIPCHK(c, hipSetDevice(c->device));
+    int A = c->A, V = c->V, Np = c->Np;
+    std::vector<double> gamma;
+    TRY(ref_rdm1(c, gamma));
+    std::vector<double> F((size_t)V * V), w, U;
+    if (V > 0) {
+        DBuf dg, dF;
+        TRY(dalloc(c, dg, sizeof(double) * A * A));
+        TRY(dalloc(c, dF, sizeof(double) * V * V));
+        HIPCHK(c, hipMemcpyAsync(dg.p, gamma.data(), sizeof(double) * A * A, hipMemcpyHostToDevice, c->stream));
+        DevProblem P = dev_problem(c);
+        hipLaunchKernelGGL(k_virtual_fock, dim3(grid1((long long)V * V, 256)), dim3(256), 0, c->stream, P,
+                           dg.as<double>(), dF.as<double>());
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipMemcpyAsync(F.data(), dF.p, sizeof(double) * V * V, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int a = 0; a < V; a++)   // exact symmetry before the eigen-decomposition
+            for (int b = a + 1; b < V; b++) {
+                double m = 0.5 * (F[(size_t)a * V + b] + F[(size_t)b * V + a]);
+                F[(size_t)a * V + b] = F[(size_t)b * V + a] = m;
+            }
+        if (!all_finite(F.data(), (long long)V * V)) FAIL(c, SCQMC_E_NUMERIC, "non-finite virtual Fock matrix");
+        jacobi_eigh(V, F, w, U);
+        // one-body operator: h' = T^T h T with T = diag(1_A, U)
+        std::vector<double> h((size_t)Np * Np), h2((size_t)Np * Np);
+        HIPCHK(c, hipMemcpyAsync(h.data(), c->heff.p, sizeof(double) * Np * Np, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        auto T = [&](int k, int j) -> double {   // T[k][j]
+            if (k < A || j < A) return k == j ? 1.0 : 0.0;
+            return U[(size_t)(k - A) * V + (j - A)];
+        };
+        for (int i = 0; i < Np; i++)
+            for (int j = 0; j < Np; j++) {
+                double s = 0.0;
+                for (int k = 0; k < Np; k++) {
+                    double tk = T(k, j);
+                    if (tk != 0.0) s += h[(size_t)i * Np + k] * tk;
+                }
+                h2[(size_t)i * Np + j] = s;
+            }
+        for (int i = 0; i < Np; i++)
+            for (int j = 0; j < Np; j++) {
+                double s = 0.0;
+                for (int k = 0; k < Np; k++) {
+                    double tk = T(k, i);
+                    if (tk != 0.0) s += tk * h2[(size_t)k * Np + j];
+                }
+                h[(size_t)i * Np + j] = s;
+            }
+        for (int i = 0; i < Np; i++)
+            for (int j = i + 1; j < Np; j++) {
+                double m = 0.5 * (h[(size_t)i * Np + j] + h[(size_t)j * Np + i]);
+                h[(size_t)i * Np + j] = h[(size_t)j * Np + i] = m;
+            }
+        HIPCHK(c, hipMemcpyAsync(c->heff.p, h.data(), sizeof(double) * Np * Np, hipMemcpyHostToDevice, c->stream));
+        // two-electron block: one index at a time
+        DBuf dU, tmp;
+        TRY(dalloc(c, dU, sizeof(double) * V * V));
+        TRY(dalloc(c, tmp, c->eri.n));
+        HIPCHK(c, hipMemcpyAsync(dU.p, U.data(), sizeof(double) * V * V, hipMemcpyHostToDevice, c->stream));
+        for (int pos = 0; pos < 4; pos++) {
+            const double *in = (pos & 1) ? tmp.as<double>() : c->eri.as<double>();
+            double *out = (pos & 1) ? c->eri.as<double>() : tmp.as<double>();
+            hipLaunchKernelGGL(k_rotate_eri, dim3(4096), dim3(256), 0, c->stream, in, out, Np, A,
+                               dU.as<double>(), pos);
+            HIPCHK(c, hipGetLastError());
+        }
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    double e0;
+    TRY(ref_energy(c, e0));
+    c->eps_h.assign(w.begin(), w.end());
+    TRY(dalloc(c, c->eps, sizeof(double) * std::max(V, 1)));
+    if (V > 0)
+        HIPCHK(c, hipMemcpyAsync(c->eps.p, c->eps_h.data(), sizeof(double) * V, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->e0_ref = e0;
+    c->has_dyall = true;
+    c->has_walkers = false;
+    if (eps_virt && V > 0) std::memcpy(eps_virt, w.data(), sizeof(double) * V);
+    if (u_out && V > 0) std::memcpy(u_out, U.data(), sizeof(double) * V * V);
+    return SCQMC_OK;
+}
+
 scqmc_status scqmc_set_options(scqmc_ctx *c, const scqmc_options *o) {
     if (!c || !o) return SCQMC_E_INVALID_ARG;
     if (!c->has_space) FAIL(c, SCQMC_E_STATE, "set_space first");
@@ -477,7 +720,6 @@ scqmc_status scqmc_set_options(scqmc_ctx *c, const scqmc_options *o) {
     return SCQMC_OK;
 }
 
-static size_t kernel_lds(const scqmc_ctx *c) { return WPB * wave_lds_bytes(lists_per_group(c)); }
 
 static scqmc_status ready_for_walkers(scqmc_ctx *c) {
     if (!c->has_coef) FAIL(c, SCQMC_E_STATE, "set_space / integrals / reference / sc_coeffs first");

@@ -808,6 +808,7 @@ __device__ void walker_eval(const DevProblem &P, const WaveLDS &L, int lane, uns
         for (int pk = 0; pk < 6; pk++) {
             Block b;
             if (!block_setup(P, W, rk, pk, b)) continue;
+            if (P.active_only && b.vp[0] + b.vp[1] > 0) continue;
             sweep_block<MOVE>(P, W, L, lane, b, wid, step, dy, a);
         }
     double E = wave_sum(a.E), G = wave_sum(a.G);

@@ -80,6 +80,9 @@ def lib():
             "scqmc_set_sc_coeffs": ([P, dbl, P, i64], C.c_int),
             "scqmc_set_dyall": ([P, P, dbl], C.c_int),
             "scqmc_set_options": ([P, C.POINTER(Options)], C.c_int),
+            "scqmc_reference_energy": ([P, C.POINTER(dbl)], C.c_int),
+            "scqmc_reference_rdm1": ([P, P], C.c_int),
+            "scqmc_semicanonicalize": ([P, P, P], C.c_int),
             "scqmc_init_walkers": ([P, i64, P, C.c_uint64], C.c_int),
             "scqmc_sample": ([P, i64], C.c_int),
             "scqmc_synchronize": ([P], C.c_int),
@@ -174,6 +177,24 @@ class Engine:
     def set_dyall(self, eps_virt, e0):
         eps_virt = _c64(eps_virt)
         self._check(lib().scqmc_set_dyall(self.h, _p(eps_virt), float(e0)))
+
+    def reference_energy(self):
+        e = C.c_double()
+        self._check(lib().scqmc_reference_energy(self.h, C.byref(e)))
+        return e.value
+
+    def reference_rdm1(self):
+        A = self.space.n_act
+        g = np.zeros(A * A)
+        self._check(lib().scqmc_reference_rdm1(self.h, _p(g)))
+        return g.reshape(A, A)
+
+    def semicanonicalize(self):
+        V = self.space.n_orb - self.space.n_core - self.space.n_act
+        eps = np.zeros(max(V, 1))
+        U = np.zeros(max(V * V, 1))
+        self._check(lib().scqmc_semicanonicalize(self.h, _p(eps), _p(U)))
+        return eps[:V], U[:V * V].reshape(V, V)
 
     def set_options(self, eps_screen=0.0, mode=0, precision=0, burn_in=0, block_len=0):
         o = Options(float(eps_screen), int(mode), int(precision), int(burn_in), int(block_len))

@@ -273,3 +273,31 @@ def count_neighbors(A, V, a_occ, v_occ):
                     cbb = cb(v_occ[1], rvb) * cb(a_occ[1], 1 - rvb) * cb(V - v_occ[1], avb) * cb(A - a_occ[1], 1 - avb)
                     total += ca * cbb
     return total
+
+
+def rdm1_active(space, basis, phi0):
+    """Spin-summed active one-particle density of phi0 (a vector over
+    ``basis``), normalised: gamma[t, u] = sum_sigma <phi0|a+_t a_u|phi0>/<phi0|phi0>,
+    by applying a_u then a+_t to every basis determinant with Jordan-Wigner signs."""
+    N, C, A = space.n_orb, space.n_core, space.n_act
+    index = {x: i for i, x in enumerate(basis)}
+    g = np.zeros((A, A))
+    for j, x in enumerate(basis):
+        if phi0[j] == 0.0:
+            continue
+        for s in range(2):
+            for u in range(A):
+                U = C + u + s * N
+                if not (x >> U) & 1:
+                    continue
+                s1 = _sign_below(x, U)
+                x1 = x ^ (1 << U)
+                for t in range(A):
+                    T = C + t + s * N
+                    if (x1 >> T) & 1:
+                        continue
+                    s2 = _sign_below(x1, T)
+                    i = index.get(x1 | (1 << T))
+                    if i is not None:
+                        g[t, u] += phi0[i] * s1 * s2 * phi0[j]
+    return g / float(phi0 @ phi0)
