@@ -156,9 +156,19 @@ __device__ __forceinline__ double phase_double(const DevProblem &P, const NDet &
     return (e & 1) ? -1.0 : 1.0;
 }
 
+// (pq|rs) = (qp|rs) = (pq|sr) = (rs|pq): the element is read at the
+// permutation that puts the largest orbital index last.  Virtual orbitals
+// carry the largest indices and are what varies from lane to lane (the rows
+// of a group differ in their virtual electrons), so neighbouring lanes read
+// neighbouring addresses and the block actually touched (e.g. (t a|u b) with
+// t, u active) stays compact instead of one cache line per element.
 __device__ __forceinline__ double eri4(const DevProblem &P, int p, int q, int r, int s) {
     unsigned Np = (unsigned)P.Np;
-    return P.eri[((p * Np + q) * Np + r) * Np + s];
+    int mpq = max(p, q), mrs = max(r, s);
+    int a = p, b = q, c = r, d = s;
+    if (mpq > mrs) { a = r; b = s; c = p; d = q; }
+    int lo = min(c, d), hi = max(c, d);
+    return P.eri[((a * Np + b) * Np + lo) * Np + hi];
 }
 // spin-orbital chemist integral (PQ|RS)
 __device__ __forceinline__ double seri(const DevProblem &P, int gP, int gQ, int gR, int gS) {

@@ -365,6 +365,13 @@ __device__ double phi1(const DevProblem &P, unsigned long long y, int s, int nl,
         acc1 += tload<U>(P.ytab.vals, oc.x + k) * fock(g_of_active(P, t), gs);
     }
     double acc = ((bs - 1) & 1) ? -acc1 : acc1;
+    // Doubles {t,u} -> {s, r}.  With Q1 < Q2 the sorted pair, the element is
+    // (Q1 P1|Q2 P2) - (Q1 P2|Q2 P1) = sgn [(s p1|r p2) - (s p2|r p1)] with
+    // sgn = +1 when s precedes r, each term present only for matching spins;
+    // read as (p2 r|p1 s) and (p1 r|p2 s) so that the virtual s, the only
+    // index that differs between the rows of a group, is the last one.
+    unsigned Np = (unsigned)P.Np, N2 = Np * Np, N3 = N2 * Np;
+    unsigned sp = (unsigned)g_idx(P, gs);
     for (int li = 1; li <= nl; li++) {
         uint2 ox = lists(li);
         unsigned cnt = ox.y & 0xFFFFFFu;
@@ -372,6 +379,9 @@ __device__ double phi1(const DevProblem &P, unsigned long long y, int s, int nl,
         int r = (int)(ox.y >> 24);
         int gr = g_of_active(P, r);
         int Q1 = gs < gr ? gs : gr, Q2 = gs < gr ? gr : gs;
+        bool s_first = gs < gr;
+        int sr = r >> 5;                         // spin of r
+        unsigned rr = (unsigned)(r & 31);
         unsigned long long yr = y & ~(1ull << r);
         for (unsigned k = 0; k < cnt; k++) {
             unsigned code = tload<U>(P.xtab.codes, ox.x + k);
@@ -382,7 +392,11 @@ __device__ double phi1(const DevProblem &P, unsigned long long y, int s, int nl,
             int br = key_below(yr | (1ull << t) | (1ull << u), r);
             int b1 = Q1 == gs ? bs : br, b2 = Q2 == gs ? bs : br;
             int e = b2 - (P1 < Q2) - (P2 < Q2) + b1 - (P1 < Q1) - (P2 < Q1);
-            double el = double_elem(P, P1, P2, Q1, Q2);
+            int st = t >> 5, su = u >> 5;
+            unsigned p1 = (unsigned)(t & 31), p2 = (unsigned)(u & 31);
+            double J = (st == sg && su == sr) ? P.eri[p2 * N3 + rr * N2 + p1 * Np + sp] : 0.0;
+            double K = (su == sg && st == sr) ? P.eri[p1 * N3 + rr * N2 + p2 * Np + sp] : 0.0;
+            double el = s_first ? J - K : K - J;
             acc += (e & 1) ? -w * el : w * el;
         }
     }
@@ -390,24 +404,28 @@ __device__ double phi1(const DevProblem &P, unsigned long long y, int s, int nl,
 }
 
 // <m|H|phi0> for m = x + virtuals s1 < s2, from the x-list of x (signed coefficients)
+// (a1 t|a2 u) is read as (t a1|u a2): the row's virtual orbitals a1, a2 give
+// a lane offset a1*Np^2 + a2, the entry's active orbitals t*Np^3 + u*Np.
 template <bool U>
 __device__ __forceinline__ double phi2(const DevProblem &P, int s1, int s2, uint2 ox) {
     int sg1 = s1 >= P.V, sg2 = s2 >= P.V;
-    int a1 = P.A + s1 - sg1 * P.V, a2 = P.A + s2 - sg2 * P.V;
+    unsigned Np = (unsigned)P.Np, N3 = Np * Np * Np;
+    unsigned a1 = (unsigned)(P.A + s1 - sg1 * P.V), a2 = (unsigned)(P.A + s2 - sg2 * P.V);
+    const double *E = P.eri + (a1 * Np) * Np + a2;
     double acc = 0.0;
     if (sg1 != sg2) {
         // alpha-beta pair: only (s1 t|s2 u) survives; spin part of the phase (-1)^(n_beta + 1)
         for (unsigned k = 0; k < ox.y; k++) {
             unsigned code = tload<U>(P.xtab.codes, ox.x + k);
-            int t = (int)((code >> 6) & 31u), u = (int)(code & 31u);
-            acc += tload<U>(P.xtab.vals, ox.x + k) * eri4(P, a1, t, a2, u);
+            unsigned t = (code >> 6) & 31u, u = code & 31u;
+            acc += tload<U>(P.xtab.vals, ox.x + k) * E[t * N3 + u * Np];
         }
         return ((P.neb + 1) & 1) ? -acc : acc;
     }
     for (unsigned k = 0; k < ox.y; k++) {
         unsigned code = tload<U>(P.xtab.codes, ox.x + k);
-        int t = (int)((code >> 6) & 31u), u = (int)(code & 31u);
-        acc += tload<U>(P.xtab.vals, ox.x + k) * (eri4(P, a1, t, a2, u) - eri4(P, a1, u, a2, t));
+        unsigned t = (code >> 6) & 31u, u = code & 31u;
+        acc += tload<U>(P.xtab.vals, ox.x + k) * (E[t * N3 + u * Np] - E[u * N3 + t * Np]);
     }
     return acc;
 }
