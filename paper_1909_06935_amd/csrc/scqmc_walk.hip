@@ -31,7 +31,11 @@
 #include "scqmc_device.h"
 
 #define WAVE 64
-#define WPB 4   // walkers (waves) per 256-thread block
+// One walker (wave) per workgroup: walkers differ widely in cost (an
+// active-space walker has several times the neighbours of a two-virtual one)
+// and a workgroup holds its LDS and registers until its last wave ends, so
+// single-wave workgroups return their slot as soon as their walker is done.
+#define WPB 1
 
 // wave-uniform values: keep them in scalar registers
 __device__ __forceinline__ unsigned uni(unsigned v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -937,7 +941,7 @@ __device__ __forceinline__ long long class_of_virt(const DevProblem &P, unsigned
     return class_id2(P.V, (int)v0, (int)v1);
 }
 
-__global__ __launch_bounds__(256, 4) void k_sample(DevProblem P, WalkerArrays S, long long W, long long step0,
+__global__ __launch_bounds__(64 * WPB, 4) void k_sample(DevProblem P, WalkerArrays S, long long W, long long step0,
                                                    int nsteps, long long burn_in, int NL) {
     extern __shared__ unsigned char smem[];
     int wave = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
@@ -988,7 +992,7 @@ __global__ __launch_bounds__(256, 4) void k_sample(DevProblem P, WalkerArrays S,
 }
 
 // local energies without moving (parity / snapshots)
-__global__ __launch_bounds__(256, 4) void k_eval(DevProblem P, const unsigned long long *keys, const unsigned *virts,
+__global__ __launch_bounds__(64 * WPB, 4) void k_eval(DevProblem P, const unsigned long long *keys, const unsigned *virts,
                                                  const int *valid, long long n, int NL, double *eloc, double *psi_out,
                                                  double *gamma, double *elocd, int *cls_out) {
     extern __shared__ unsigned char smem[];
