@@ -297,17 +297,38 @@ __device__ __forceinline__ double wphase_double(const WaveLDS &L, int P1, int P2
 // single P -> Q from the walker: returns the element with every non-core
 // electron in the sum; *act receives the sum over active electrons only
 // (Dyall's H_0)
+// Coulomb and exchange integrals of electron j with the pair (p, q), lo/hi
+// = min/max(p, q):  (jj|pq) at j (Np^3 + Np^2) + lo Np + hi and
+// (pj|jq) = (lo j|j hi) at lo Np^3 + hi + j (Np^2 + Np): two multiply-adds
+// per electron, the largest (virtual) index last.
+struct JKOff {
+    unsigned offJ, offK, cJ, cK;
+};
+__device__ __forceinline__ JKOff jk_offsets(const DevProblem &P, int p, int q) {
+    unsigned Np = (unsigned)P.Np, N2 = Np * Np, N3 = N2 * Np;
+    unsigned lo = (unsigned)min(p, q), hi = (unsigned)max(p, q);
+    JKOff o;
+    o.offJ = lo * Np + hi;
+    o.offK = lo * N3 + hi;
+    o.cJ = N3 + N2;
+    o.cK = N2 + Np;
+    return o;
+}
+__device__ __forceinline__ double jk_term(const DevProblem &P, const JKOff &o, int j, bool same_spin) {
+    double J = P.eri[(unsigned)j * o.cJ + o.offJ];
+    double K = same_spin ? P.eri[(unsigned)j * o.cK + o.offK] : 0.0;
+    return J - K;
+}
+
 __device__ __forceinline__ double single_elem_w2(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, int gP,
                                                  int gQ, double *act) {
     int p = g_idx(P, gP), q = g_idx(P, gQ), sp = g_spin(P, gP);
+    JKOff o = jk_offsets(P, p, q);
     double v = P.heff[q * P.Np + p];
 #pragma unroll 4
     for (int i = 0; i < W.ne; i++) {
         int gJ = L.wg[i];
-        int j = g_idx(P, gJ);
-        double J = eri4(P, j, j, p, q);
-        double K = eri4(P, p, j, j, q);
-        double t = J - (g_spin(P, gJ) == sp ? K : 0.0);
+        double t = jk_term(P, o, g_idx(P, gJ), g_spin(P, gJ) == sp);
         v += (gJ == gP) ? 0.0 : t;
     }
     *act = v;
@@ -316,10 +337,7 @@ __device__ __forceinline__ double single_elem_w2(const DevProblem &P, const Walk
         if (i >= W.n.nv) break;
         int gJ = W.n.vg[i];
         if (gJ == gP) continue;
-        int j = g_idx(P, gJ);
-        double J = eri4(P, j, j, p, q);
-        double K = (g_spin(P, gJ) == sp) ? eri4(P, p, j, j, q) : 0.0;
-        v += J - K;
+        v += jk_term(P, o, g_idx(P, gJ), g_spin(P, gJ) == sp);
     }
     return v;
 }
@@ -329,24 +347,19 @@ __device__ __forceinline__ double single_elem_w2(const DevProblem &P, const Walk
 __device__ __forceinline__ double fock_y(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, int r0,
                                          int r1, int p0, int p1, int gT, int gS) {
     int t = g_idx(P, gT), s = g_idx(P, gS), st = g_spin(P, gT);
+    JKOff o = jk_offsets(P, t, s);
     double v = P.heff[s * P.Np + t];
 #pragma unroll 4
     for (int i = 0; i < W.ne; i++) {
         int gJ = L.wg[i];
-        int j = g_idx(P, gJ);
-        double J = eri4(P, j, j, t, s);
-        double K = eri4(P, t, j, j, s);
-        double x = J - (g_spin(P, gJ) == st ? K : 0.0);
+        double x = jk_term(P, o, g_idx(P, gJ), g_spin(P, gJ) == st);
         v += (gJ == r0 || gJ == r1) ? 0.0 : x;
     }
 #pragma unroll
     for (int i = 0; i < 2; i++) {
         int gJ = i ? p1 : p0;
         if (gJ < 0) continue;
-        int j = g_idx(P, gJ);
-        double J = eri4(P, j, j, t, s);
-        double K = (g_spin(P, gJ) == st) ? eri4(P, t, j, j, s) : 0.0;
-        v += J - K;
+        v += jk_term(P, o, g_idx(P, gJ), g_spin(P, gJ) == st);
     }
     return v;
 }
