@@ -640,10 +640,29 @@ __device__ __forceinline__ void row_eval_any(const DevProblem &P, const WalkerCt
     else row_eval<2, U>(P, W, L, d, G, o);
 }
 
+// Sum over the 64 lanes of a wave with DPP moves (no LDS round trips):
+// prefix sums inside each row of 16 lanes (row_shr 1, 2, 4, 8), then row
+// totals carried across rows (row_bcast 15 into rows 1 and 3, row_bcast 31
+// into rows 2 and 3).  Lane 63 ends with the total, which is returned
+// wave-uniform.  Fixed order of additions, so the result is deterministic.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_d(double v) {
+    long long b = __double_as_longlong(v);
+    int lo = (int)b, hi = (int)(b >> 32);
+    lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROWS, 0xf, false);
+    hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROWS, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
-    return v;
+    v += dpp_d<0x111, 0xf>(v);   // row_shr:1
+    v += dpp_d<0x112, 0xf>(v);   // row_shr:2
+    v += dpp_d<0x114, 0xf>(v);   // row_shr:4
+    v += dpp_d<0x118, 0xf>(v);   // row_shr:8
+    v += dpp_d<0x142, 0xa>(v);   // row_bcast:15 -> rows 1, 3
+    v += dpp_d<0x143, 0xc>(v);   // row_bcast:31 -> rows 2, 3
+    long long b = __double_as_longlong(v);
+    int lo = __builtin_amdgcn_readlane((int)b, 63), hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
 __device__ inline void walker_setup(const DevProblem &P, const WaveLDS &L, int lane, unsigned long long key,
