@@ -133,6 +133,8 @@ def main():
     ap.add_argument("--config", default="cfg2", choices=["cfg2", "cfg3"])
     ap.add_argument("--walkers", type=int, default=0)
     ap.add_argument("--block", type=int, default=1, help="steps per kernel launch")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
+                    help="fp32: the precision form (FP32 off-diagonal Slater-Condon terms, FP64 sums)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg (and the roofline count)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (HBM counter calibration)")
@@ -160,6 +162,8 @@ def main():
     W = args.walkers or wl.CONFIGS[args.config]["walkers"]
     stream = torch.cuda.Stream()
     eng = Engine.from_problem(prob, mode=1, burn_in=args.warmup, block_len=args.block, stream=stream)
+    if args.precision == "fp32":
+        eng.set_options(mode=1, precision=1, burn_in=args.warmup, block_len=args.block)
     if prob.e0_ref == 0.0:
         # no stored CAS energy for this workload: E_0^(0) of its reference, on the device
         eng.set_dyall(prob.eps_virt, eng.reference_energy())
@@ -199,7 +203,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32 terms, f64 sums",
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.config], "walkers": W, "steps_per_launch": args.block},
         "estimates": {k: est[k] for k in ("e_var", "e_var_err", "a0_sq", "e2")},

@@ -73,7 +73,12 @@ typedef struct {
                              section); 0 = keep every double */
     int32_t mode;         /* 0: local energy (SC-MRCI); 1: also the Dyall local energy and
                              the per-class NEVPT2 sums of eq:nevpt (needs set_dyall) */
-    int32_t precision;    /* 0: FP64 (the only form implemented; others -> UNSUPPORTED) */
+    int32_t precision;    /* 0: FP64.  1: precision form -- the off-diagonal Slater-Condon
+                             elements and the terms of every overlap psi(m) are computed
+                             in FP32 from FP32 copies of the integrals (made on first use)
+                             and summed in FP64; H_nn, psi(n) of the walker, the
+                             accumulators and the estimators stay FP64.  Changing it
+                             invalidates placed walkers.  Other values -> INVALID_ARG. */
     int64_t burn_in;      /* global step index from which estimators accumulate */
     int64_t block_len;    /* steps per kernel launch inside scqmc_sample (0 = all) */
 } scqmc_options;

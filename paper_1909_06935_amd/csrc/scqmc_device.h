@@ -36,6 +36,8 @@ struct DevProblem {
     double eps_screen;      // doubles with |<rs||pq>| <= eps are left out (0: keep all)
     const double *heff;     // [Np*Np] core-folded one-body operator
     const double *eri;      // [Np^4] (pq|rs) over non-core orbitals
+    const float *heff32;    // FP32 copies for the precision form (null in FP64 runs)
+    const float *eri32;
     const double *ccls;     // [ncls] SC coefficients, c0 at index 0
     const double *eps;      // [V] Dyall virtual orbital energies (mode 1)
     DevTable ref, ytab, xtab;
@@ -156,36 +158,53 @@ __device__ __forceinline__ double phase_double(const DevProblem &P, const NDet &
     return (e & 1) ? -1.0 : 1.0;
 }
 
+// Integral storage of the two forms of the walk: FP64 (R = double) or the
+// precision form, whose off-diagonal Slater-Condon terms are computed in
+// FP32 (R = float) from FP32 copies and added to FP64 sums.
+template <class R> struct Ints;
+template <> struct Ints<double> {
+    static __device__ __forceinline__ const double *eri(const DevProblem &P) { return P.eri; }
+    static __device__ __forceinline__ const double *heff(const DevProblem &P) { return P.heff; }
+};
+template <> struct Ints<float> {
+    static __device__ __forceinline__ const float *eri(const DevProblem &P) { return P.eri32; }
+    static __device__ __forceinline__ const float *heff(const DevProblem &P) { return P.heff32; }
+};
+
 // (pq|rs) = (qp|rs) = (pq|sr) = (rs|pq): the element is read at the
 // permutation that puts the largest orbital index last.  Virtual orbitals
 // carry the largest indices and are what varies from lane to lane (the rows
 // of a group differ in their virtual electrons), so neighbouring lanes read
 // neighbouring addresses and the block actually touched (e.g. (t a|u b) with
 // t, u active) stays compact instead of one cache line per element.
-__device__ __forceinline__ double eri4(const DevProblem &P, int p, int q, int r, int s) {
+template <class R = double>
+__device__ __forceinline__ R eri4(const DevProblem &P, int p, int q, int r, int s) {
     unsigned Np = (unsigned)P.Np;
     int mpq = max(p, q), mrs = max(r, s);
     int a = p, b = q, c = r, d = s;
     if (mpq > mrs) { a = r; b = s; c = p; d = q; }
     int lo = min(c, d), hi = max(c, d);
-    return P.eri[((a * Np + b) * Np + lo) * Np + hi];
+    return Ints<R>::eri(P)[((a * Np + b) * Np + lo) * Np + hi];
 }
 // spin-orbital chemist integral (PQ|RS)
-__device__ __forceinline__ double seri(const DevProblem &P, int gP, int gQ, int gR, int gS) {
-    if (g_spin(P, gP) != g_spin(P, gQ) || g_spin(P, gR) != g_spin(P, gS)) return 0.0;
-    return eri4(P, g_idx(P, gP), g_idx(P, gQ), g_idx(P, gR), g_idx(P, gS));
+template <class R = double>
+__device__ __forceinline__ R seri(const DevProblem &P, int gP, int gQ, int gR, int gS) {
+    if (g_spin(P, gP) != g_spin(P, gQ) || g_spin(P, gR) != g_spin(P, gS)) return R(0);
+    return eri4<R>(P, g_idx(P, gP), g_idx(P, gQ), g_idx(P, gR), g_idx(P, gS));
 }
 // <Q1 Q2 || P1 P2> piece of a double: (Q1 P1|Q2 P2) - (Q1 P2|Q2 P1)
-__device__ __forceinline__ double double_elem(const DevProblem &P, int P1, int P2, int Q1, int Q2) {
-    return seri(P, Q1, P1, Q2, P2) - seri(P, Q1, P2, Q2, P1);
+template <class R = double>
+__device__ __forceinline__ R double_elem(const DevProblem &P, int P1, int P2, int Q1, int Q2) {
+    return seri<R>(P, Q1, P1, Q2, P2) - seri<R>(P, Q1, P2, Q2, P1);
 }
 
 // one-body part of a single P -> Q from determinant b:
 // h_eff[Q][P] + sum_{J in b, J != P} [(QP|JJ) - (QJ|JP)]; with_virt = 0 drops
 // the virtual electrons from the sum (Dyall's H_0 acts on the active space only)
+template <class R = double>
 __device__ __forceinline__ double single_elem(const DevProblem &P, const NDet &b, int gP, int gQ, bool with_virt) {
     int p = g_idx(P, gP), q = g_idx(P, gQ), sp = g_spin(P, gP);
-    double v = P.heff[q * P.Np + p];
+    double v = (double)Ints<R>::heff(P)[q * P.Np + p];
     for (int s = 0; s < 2; s++) {
         uint32_t act = (uint32_t)(b.key >> (32 * s));
         while (act) {
@@ -194,9 +213,9 @@ __device__ __forceinline__ double single_elem(const DevProblem &P, const NDet &b
             int gJ = s * P.Np + t;
             if (gJ == gP) continue;
             // (qp|jj) = (jj|pq) and (qj|jp) = (pj|jq): the lane-varying index goes last
-            double J = eri4(P, t, t, p, q);
-            double K = (s == sp) ? eri4(P, p, t, t, q) : 0.0;
-            v += J - K;
+            R J = eri4<R>(P, t, t, p, q);
+            R K = (s == sp) ? eri4<R>(P, p, t, t, q) : R(0);
+            v += (double)(J - K);
         }
     }
     if (with_virt) {
@@ -206,9 +225,9 @@ __device__ __forceinline__ double single_elem(const DevProblem &P, const NDet &b
             int gJ = b.vg[i];
             if (gJ == gP) continue;
             int j = g_idx(P, gJ), s = g_spin(P, gJ);
-            double J = eri4(P, j, j, p, q);
-            double K = (s == sp) ? eri4(P, p, j, j, q) : 0.0;
-            v += J - K;
+            R J = eri4<R>(P, j, j, p, q);
+            R K = (s == sp) ? eri4<R>(P, p, j, j, q) : R(0);
+            v += (double)(J - K);
         }
     }
     return v;

@@ -64,6 +64,8 @@ struct scqmc_ctx {
     scqmc_options opt{0.0, 0, 0, 0, 0};
     double e_core = 0.0, e0_ref = 0.0;
     DBuf heff, eri, ccls, eps, refcoef, refkey;
+    DBuf heff32, eri32;                  // precision form: FP32 copies
+    long long ints_version = 0, f32_version = -1;
     std::vector<double> refcoef_h;
     TableBufs ref, ytab, xtab;
     long long n_ref = 0;
@@ -127,6 +129,8 @@ static DevProblem dev_problem(const scqmc_ctx *c) {
     P.eps_screen = c->opt.eps_screen;
     P.heff = c->heff.as<double>();
     P.eri = c->eri.as<double>();
+    P.heff32 = c->heff32.as<float>();
+    P.eri32 = c->eri32.as<float>();
     P.ccls = c->ccls.as<double>();
     P.eps = c->eps.as<double>();
     P.ref = c->ref.view();
@@ -265,6 +269,22 @@ static scqmc_status finish_integrals(scqmc_ctx *c, DBuf &full, DBuf &h1d, double
     HIPCHK(c, hipMemcpyAsync(&c->e_core, ec.p, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->has_ints = true;
+    c->ints_version++;
+    return SCQMC_OK;
+}
+
+// FP32 copies of the integrals for the precision form, made on demand and
+// again whenever the integrals changed (set_integrals_*, semicanonicalize).
+static scqmc_status ensure_f32(scqmc_ctx *c) {
+    if (c->opt.precision != 1 || c->f32_version == c->ints_version) return SCQMC_OK;
+    long long Np4 = (long long)c->Np * c->Np * c->Np * c->Np, Np2 = (long long)c->Np * c->Np;
+    TRY(dalloc(c, c->eri32, sizeof(float) * Np4));
+    TRY(dalloc(c, c->heff32, sizeof(float) * Np2));
+    hipLaunchKernelGGL(k_to_f32, dim3(4096), dim3(256), 0, c->stream, c->eri.as<double>(), c->eri32.as<float>(), Np4);
+    hipLaunchKernelGGL(k_to_f32, dim3(grid1(Np2, 256)), dim3(256), 0, c->stream, c->heff.as<double>(),
+                       c->heff32.as<float>(), Np2);
+    HIPCHK(c, hipGetLastError());
+    c->f32_version = c->ints_version;
     return SCQMC_OK;
 }
 
@@ -529,7 +549,7 @@ static scqmc_status ref_energy(scqmc_ctx *c, double &e0) {
     P.eps_screen = 0.0;
     P.active_only = 1;
     int NL = lists_per_group(c);
-    hipLaunchKernelGGL(k_eval, dim3(grid1(n, WPB)), dim3(64 * WPB), kernel_lds(c), c->stream, P,
+    hipLaunchKernelGGL(k_eval<double>, dim3(grid1(n, WPB)), dim3(64 * WPB), kernel_lds(c), c->stream, P,
                        c->refkey.as<unsigned long long>(), virt.as<unsigned>(), valid.as<int>(), n, NL,
                        eloc.as<double>(), (double *)nullptr, (double *)nullptr, (double *)nullptr, (int *)nullptr);
     HIPCHK(c, hipGetLastError());
@@ -693,6 +713,7 @@ scqmc_status scqmc_semicanonicalize(scqmc_ctx *c, double *eps_virt, double *u_ou
             HIPCHK(c, hipGetLastError());
         }
         HIPCHK(c, hipStreamSynchronize(c->stream));
+        c->ints_version++;
     }
     double e0;
     TRY(ref_energy(c, e0));
@@ -714,8 +735,10 @@ scqmc_status scqmc_set_options(scqmc_ctx *c, const scqmc_options *o) {
     if (!c->has_space) FAIL(c, SCQMC_E_STATE, "set_space first");
     if (!std::isfinite(o->eps_screen) || o->eps_screen < 0) FAIL(c, SCQMC_E_INVALID_ARG, "eps_screen must be >= 0");
     if (o->mode != 0 && o->mode != 1) FAIL(c, SCQMC_E_INVALID_ARG, "mode must be 0 or 1");
-    if (o->precision != 0) FAIL(c, SCQMC_E_UNSUPPORTED, "only the FP64 form is implemented");
+    if (o->precision != 0 && o->precision != 1) FAIL(c, SCQMC_E_INVALID_ARG, "precision must be 0 (FP64) or 1 (FP32 form)");
     if (o->burn_in < 0 || o->block_len < 0) FAIL(c, SCQMC_E_INVALID_ARG, "negative burn_in / block_len");
+    // walkers carry psi(n) of the form they were placed with
+    if (o->precision != c->opt.precision) c->has_walkers = false;
     c->opt = *o;
     return SCQMC_OK;
 }
@@ -752,9 +775,14 @@ scqmc_status scqmc_init_walkers(scqmc_ctx *c, int64_t W, const uint64_t *dets, u
     HIPCHK(c, hipMemsetAsync(c->cacc.p, 0, class_acc_bytes(c), c->stream));
     HIPCHK(c, hipMemsetAsync(c->bad.p, 0, sizeof(unsigned long long), c->stream));
     c->seed = seed;
+    TRY(ensure_f32(c));
     DevProblem P = dev_problem(c);
-    hipLaunchKernelGGL(k_psi, dim3(grid1(W, 64)), dim3(64), 0, c->stream, P, c->wkey.as<unsigned long long>(),
-                       c->wvirt.as<unsigned>(), (long long)W, c->wpsi.as<double>());
+    if (c->opt.precision == 1)
+        hipLaunchKernelGGL(k_psi<float>, dim3(grid1(W, 64)), dim3(64), 0, c->stream, P,
+                           c->wkey.as<unsigned long long>(), c->wvirt.as<unsigned>(), (long long)W, c->wpsi.as<double>());
+    else
+        hipLaunchKernelGGL(k_psi<double>, dim3(grid1(W, 64)), dim3(64), 0, c->stream, P,
+                           c->wkey.as<unsigned long long>(), c->wvirt.as<unsigned>(), (long long)W, c->wpsi.as<double>());
     HIPCHK(c, hipGetLastError());
     std::vector<double> psi(W);
     HIPCHK(c, hipMemcpyAsync(psi.data(), c->wpsi.p, sizeof(double) * W, hipMemcpyDeviceToHost, c->stream));
@@ -776,6 +804,7 @@ scqmc_status scqmc_sample(scqmc_ctx *c, int64_t n_steps) {
     if (n_steps < 0) FAIL(c, SCQMC_E_INVALID_ARG, "negative n_steps");
     if (c->step + n_steps >= (1LL << 31)) FAIL(c, SCQMC_E_UNSUPPORTED, "step counter limit (2^31) reached");
     HIPCHK(c, hipSetDevice(c->device));
+    TRY(ensure_f32(c));
     DevProblem P = dev_problem(c);
     WalkerArrays S;
     S.key = c->wkey.as<unsigned long long>();
@@ -790,8 +819,12 @@ scqmc_status scqmc_sample(scqmc_ctx *c, int64_t n_steps) {
     long long blk = c->opt.block_len > 0 ? c->opt.block_len : 1;
     for (long long done = 0; done < n_steps; done += blk) {
         int ns = (int)std::min(blk, n_steps - done);
-        hipLaunchKernelGGL(k_sample, dim3(grid1(c->W, WPB)), dim3(64 * WPB), lds, c->stream, P, S, c->W,
-                           c->step + done, ns, (long long)c->opt.burn_in, NL);
+        if (c->opt.precision == 1)
+            hipLaunchKernelGGL(k_sample<float>, dim3(grid1(c->W, WPB)), dim3(64 * WPB), lds, c->stream, P, S, c->W,
+                               c->step + done, ns, (long long)c->opt.burn_in, NL);
+        else
+            hipLaunchKernelGGL(k_sample<double>, dim3(grid1(c->W, WPB)), dim3(64 * WPB), lds, c->stream, P, S, c->W,
+                               c->step + done, ns, (long long)c->opt.burn_in, NL);
         HIPCHK(c, hipGetLastError());
     }
     c->step += n_steps;
@@ -998,12 +1031,18 @@ scqmc_status scqmc_eval_snapshot(scqmc_ctx *c, int64_t n, const uint64_t *d_dets
     hipLaunchKernelGGL(k_compact, dim3(grid1(n, 128)), dim3(128), 0, c->stream, (const unsigned long long *)d_dets,
                        (long long)n, c->words, c->N, c->C, c->A, c->na, c->nb, c->skey.as<unsigned long long>(),
                        c->svirt.as<unsigned>(), c->svalid.as<int>());
+    TRY(ensure_f32(c));
     DevProblem P = dev_problem(c);
     int NL = lists_per_group(c);
-    hipLaunchKernelGGL(k_eval, dim3(grid1(n, WPB)), dim3(64 * WPB), kernel_lds(c), c->stream, P,
-                       c->skey.as<unsigned long long>(), c->svirt.as<unsigned>(), c->svalid.as<int>(), (long long)n,
-                       NL, d_eloc, d_psi, d_gamma, (c->opt.mode == 1 && c->has_dyall) ? d_eloc_dyall : nullptr,
-                       (int *)d_class);
+    double *d_eld = (c->opt.mode == 1 && c->has_dyall) ? d_eloc_dyall : nullptr;
+    if (c->opt.precision == 1)
+        hipLaunchKernelGGL(k_eval<float>, dim3(grid1(n, WPB)), dim3(64 * WPB), kernel_lds(c), c->stream, P,
+                           c->skey.as<unsigned long long>(), c->svirt.as<unsigned>(), c->svalid.as<int>(),
+                           (long long)n, NL, d_eloc, d_psi, d_gamma, d_eld, (int *)d_class);
+    else
+        hipLaunchKernelGGL(k_eval<double>, dim3(grid1(n, WPB)), dim3(64 * WPB), kernel_lds(c), c->stream, P,
+                           c->skey.as<unsigned long long>(), c->svirt.as<unsigned>(), c->svalid.as<int>(),
+                           (long long)n, NL, d_eloc, d_psi, d_gamma, d_eld, (int *)d_class);
     HIPCHK(c, hipGetLastError());
     if (d_eloc_dyall && !(c->opt.mode == 1 && c->has_dyall)) {
         std::vector<double> nanv(n, NAN);

@@ -187,3 +187,9 @@ __global__ void k_fill_slots(ulonglong2 *s, long long n) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) s[i] = make_ulonglong2(SCQ_EMPTY_KEY, 0ull);
 }
+
+// FP32 copy of an FP64 array (the precision form's integrals)
+__global__ void k_to_f32(const double *in, float *out, long long n) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        out[i] = (float)in[i];
+}

@@ -314,21 +314,24 @@ __device__ __forceinline__ JKOff jk_offsets(const DevProblem &P, int p, int q) {
     o.cK = N2 + Np;
     return o;
 }
-__device__ __forceinline__ double jk_term(const DevProblem &P, const JKOff &o, int j, bool same_spin) {
-    double J = P.eri[(unsigned)j * o.cJ + o.offJ];
-    double K = same_spin ? P.eri[(unsigned)j * o.cK + o.offK] : 0.0;
+template <class R>
+__device__ __forceinline__ R jk_term(const DevProblem &P, const JKOff &o, int j, bool same_spin) {
+    const R *E = Ints<R>::eri(P);
+    R J = E[(unsigned)j * o.cJ + o.offJ];
+    R K = same_spin ? E[(unsigned)j * o.cK + o.offK] : R(0);
     return J - K;
 }
 
+template <class R>
 __device__ __forceinline__ double single_elem_w2(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, int gP,
                                                  int gQ, double *act) {
     int p = g_idx(P, gP), q = g_idx(P, gQ), sp = g_spin(P, gP);
     JKOff o = jk_offsets(P, p, q);
-    double v = P.heff[q * P.Np + p];
+    double v = (double)Ints<R>::heff(P)[q * P.Np + p];
 #pragma unroll 4
     for (int i = 0; i < W.ne; i++) {
         int gJ = L.wg[i];
-        double t = jk_term(P, o, g_idx(P, gJ), g_spin(P, gJ) == sp);
+        double t = (double)jk_term<R>(P, o, g_idx(P, gJ), g_spin(P, gJ) == sp);
         v += (gJ == gP) ? 0.0 : t;
     }
     *act = v;
@@ -337,29 +340,30 @@ __device__ __forceinline__ double single_elem_w2(const DevProblem &P, const Walk
         if (i >= W.n.nv) break;
         int gJ = W.n.vg[i];
         if (gJ == gP) continue;
-        v += jk_term(P, o, g_idx(P, gJ), g_spin(P, gJ) == sp);
+        v += (double)jk_term<R>(P, o, g_idx(P, gJ), g_spin(P, gJ) == sp);
     }
     return v;
 }
 
 // h_eff[s][t] + sum_{j in y} [(st|jj) - delta (sj|jt)] with y = x_n - Ra + Pa,
 // iterated as the walker's active electrons minus Ra plus Pa
+template <class R>
 __device__ __forceinline__ double fock_y(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, int r0,
                                          int r1, int p0, int p1, int gT, int gS) {
     int t = g_idx(P, gT), s = g_idx(P, gS), st = g_spin(P, gT);
     JKOff o = jk_offsets(P, t, s);
-    double v = P.heff[s * P.Np + t];
+    double v = (double)Ints<R>::heff(P)[s * P.Np + t];
 #pragma unroll 4
     for (int i = 0; i < W.ne; i++) {
         int gJ = L.wg[i];
-        double x = jk_term(P, o, g_idx(P, gJ), g_spin(P, gJ) == st);
+        double x = (double)jk_term<R>(P, o, g_idx(P, gJ), g_spin(P, gJ) == st);
         v += (gJ == r0 || gJ == r1) ? 0.0 : x;
     }
 #pragma unroll
     for (int i = 0; i < 2; i++) {
         int gJ = i ? p1 : p0;
         if (gJ < 0) continue;
-        v += jk_term(P, o, g_idx(P, gJ), g_spin(P, gJ) == st);
+        v += (double)jk_term<R>(P, o, g_idx(P, gJ), g_spin(P, gJ) == st);
     }
     return v;
 }
@@ -370,7 +374,7 @@ __device__ __forceinline__ double fock_y(const DevProblem &P, const WalkerCtx &W
 // electron r only.  `fock` gives the single-excitation element.
 // lists(0) is the y-list of y; lists(1..nl) are x-lists of y - r with r in
 // the top byte of .y (ascending r; empty ones may be left out).
-template <bool U, class ListFn, class FockFn>
+template <bool U, class R, class ListFn, class FockFn>
 __device__ double phi1(const DevProblem &P, unsigned long long y, int s, int nl, ListFn lists, FockFn fock) {
     int sg = s >= P.V;
     int gs = g_of_virtual(P, s);
@@ -389,6 +393,7 @@ __device__ double phi1(const DevProblem &P, unsigned long long y, int s, int nl,
     // index that differs between the rows of a group, is the last one.
     unsigned Np = (unsigned)P.Np, N2 = Np * Np, N3 = N2 * Np;
     unsigned sp = (unsigned)g_idx(P, gs);
+    const R *E = Ints<R>::eri(P);
     for (int li = 1; li <= nl; li++) {
         uint2 ox = lists(li);
         unsigned cnt = ox.y & 0xFFFFFFu;
@@ -411,9 +416,9 @@ __device__ double phi1(const DevProblem &P, unsigned long long y, int s, int nl,
             int e = b2 - (P1 < Q2) - (P2 < Q2) + b1 - (P1 < Q1) - (P2 < Q1);
             int st = t >> 5, su = u >> 5;
             unsigned p1 = (unsigned)(t & 31), p2 = (unsigned)(u & 31);
-            double J = (st == sg && su == sr) ? P.eri[p2 * N3 + rr * N2 + p1 * Np + sp] : 0.0;
-            double K = (su == sg && st == sr) ? P.eri[p1 * N3 + rr * N2 + p2 * Np + sp] : 0.0;
-            double el = s_first ? J - K : K - J;
+            R J = (st == sg && su == sr) ? E[p2 * N3 + rr * N2 + p1 * Np + sp] : R(0);
+            R K = (su == sg && st == sr) ? E[p1 * N3 + rr * N2 + p2 * Np + sp] : R(0);
+            double el = (double)(s_first ? J - K : K - J);
             acc += (e & 1) ? -w * el : w * el;
         }
     }
@@ -423,31 +428,32 @@ __device__ double phi1(const DevProblem &P, unsigned long long y, int s, int nl,
 // <m|H|phi0> for m = x + virtuals s1 < s2, from the x-list of x (signed coefficients)
 // (a1 t|a2 u) is read as (t a1|u a2): the row's virtual orbitals a1, a2 give
 // a lane offset a1*Np^2 + a2, the entry's active orbitals t*Np^3 + u*Np.
-template <bool U>
+template <bool U, class R>
 __device__ __forceinline__ double phi2(const DevProblem &P, int s1, int s2, uint2 ox) {
     int sg1 = s1 >= P.V, sg2 = s2 >= P.V;
     unsigned Np = (unsigned)P.Np, N3 = Np * Np * Np;
     unsigned a1 = (unsigned)(P.A + s1 - sg1 * P.V), a2 = (unsigned)(P.A + s2 - sg2 * P.V);
-    const double *E = P.eri + (a1 * Np) * Np + a2;
+    const R *E = Ints<R>::eri(P) + (a1 * Np) * Np + a2;
     double acc = 0.0;
     if (sg1 != sg2) {
         // alpha-beta pair: only (s1 t|s2 u) survives; spin part of the phase (-1)^(n_beta + 1)
         for (unsigned k = 0; k < ox.y; k++) {
             unsigned code = tload<U>(P.xtab.codes, ox.x + k);
             unsigned t = (code >> 6) & 31u, u = code & 31u;
-            acc += tload<U>(P.xtab.vals, ox.x + k) * E[t * N3 + u * Np];
+            acc += tload<U>(P.xtab.vals, ox.x + k) * (double)E[t * N3 + u * Np];
         }
         return ((P.neb + 1) & 1) ? -acc : acc;
     }
     for (unsigned k = 0; k < ox.y; k++) {
         unsigned code = tload<U>(P.xtab.codes, ox.x + k);
         unsigned t = (code >> 6) & 31u, u = code & 31u;
-        acc += tload<U>(P.xtab.vals, ox.x + k) * (E[t * N3 + u * Np] - E[u * N3 + t * Np]);
+        acc += tload<U>(P.xtab.vals, ox.x + k) * (double)(E[t * N3 + u * Np] - E[u * N3 + t * Np]);
     }
     return acc;
 }
 
 // psi of one determinant with its own lookups (one lane; initialisation / snapshots)
+template <class R>
 __device__ double psi_direct(const DevProblem &P, unsigned long long key, unsigned virt) {
     int vcode[2] = {(int)(virt & 0xFFFFu), (int)(virt >> 16)};
     int nv = (vcode[0] != (int)SCQ_NOVIRT) + (vcode[1] != (int)SCQ_NOVIRT);
@@ -456,7 +462,7 @@ __device__ double psi_direct(const DevProblem &P, unsigned long long key, unsign
         return oc.y ? P.ccls[0] * P.ref.vals[oc.x] : 0.0;
     }
     if (nv == 1) {
-        double phi = phi1<false>(
+        double phi = phi1<false, R>(
             P, key, vcode[0], popc64(key),
             [&](int k) -> uint2 {
                 if (k == 0) return table_find(P.ytab, key);
@@ -471,11 +477,11 @@ __device__ double psi_direct(const DevProblem &P, unsigned long long key, unsign
                 d.nv = 0;
                 d.vg[0] = d.vg[1] = SCQ_NOG;
                 d.key = key | (1ull << ((gT >= P.Np ? 32 : 0) + g_idx(P, gT)));
-                return single_elem(P, d, gT, gS, false);
+                return single_elem<R>(P, d, gT, gS, false);
             });
         return P.ccls[class_id1(P.V, vcode[0])] * phi;
     }
-    return P.ccls[class_id2(P.V, vcode[0], vcode[1])] * phi2<false>(P, vcode[0], vcode[1], table_find(P.xtab, key));
+    return P.ccls[class_id2(P.V, vcode[0], vcode[1])] * phi2<false, R>(P, vcode[0], vcode[1], table_find(P.xtab, key));
 }
 
 // Row r of a block, independent of the group: the virtual set of m, its
@@ -596,7 +602,7 @@ __device__ __forceinline__ uint2 view_list(const GroupView &v, int k) {
 }
 
 // row d of group G: <m|H|n>, psi(m), the Dyall element if m keeps n's virtual set
-template <int VP, bool U>
+template <int VP, bool U, class R>
 __device__ __forceinline__ void row_eval(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L,
                                          const RowDec &d, const GroupView &G, RowRes &o) {
     // outer excitation n -> m: removed P*, added Q* (ascending spin-orbital order)
@@ -611,12 +617,12 @@ __device__ __forceinline__ void row_eval(const DevProblem &P, const WalkerCtx &W
         double ph = wphase_single(L, Pr0, Qa0);
         double act;
         o.phase = ph;
-        o.hnm = ph * single_elem_w2(P, W, L, Pr0, Qa0, &act);
+        o.hnm = ph * single_elem_w2<R>(P, W, L, Pr0, Qa0, &act);
         o.hd = ph * act;
     } else {
         double ph = wphase_double(L, Pr0, Pr1, Qa0, Qa1);
         o.phase = ph;
-        o.hnm = ph * double_elem(P, Pr0, Pr1, Qa0, Qa1);
+        o.hnm = ph * (double)double_elem<R>(P, Pr0, Pr1, Qa0, Qa1);
         o.hd = o.hnm;
         if (P.eps_screen > 0.0 && !(fabs(o.hnm) > P.eps_screen)) { o.ok = false; o.psi = 0.0; return; }
     }
@@ -624,20 +630,20 @@ __device__ __forceinline__ void row_eval(const DevProblem &P, const WalkerCtx &W
     if (VP == 0) {
         phi = G.phi;
     } else if (VP == 1) {
-        phi = phi1<U>(P, G.xkey, d.Lp0, G.nl, [&](int k) -> uint2 { return view_list<U>(G, k); },
-                      [&](int gT, int gS) -> double { return fock_y(P, W, L, G.rg0, G.rg1, G.pg0, G.pg1, gT, gS); });
+        phi = phi1<U, R>(P, G.xkey, d.Lp0, G.nl, [&](int k) -> uint2 { return view_list<U>(G, k); },
+                         [&](int gT, int gS) -> double { return fock_y<R>(P, W, L, G.rg0, G.rg1, G.pg0, G.pg1, gT, gS); });
     } else {
-        phi = phi2<U>(P, d.Lp0, d.Lp1, view_list<U>(G, 0));
+        phi = phi2<U, R>(P, d.Lp0, d.Lp1, view_list<U>(G, 0));
     }
     o.psi = d.c * phi;
 }
 
-template <bool U>
+template <bool U, class R>
 __device__ __forceinline__ void row_eval_any(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, int vp,
                                              const RowDec &d, const GroupView &G, RowRes &o) {
-    if (vp == 0) row_eval<0, U>(P, W, L, d, G, o);
-    else if (vp == 1) row_eval<1, U>(P, W, L, d, G, o);
-    else row_eval<2, U>(P, W, L, d, G, o);
+    if (vp == 0) row_eval<0, U, R>(P, W, L, d, G, o);
+    else if (vp == 1) row_eval<1, U, R>(P, W, L, d, G, o);
+    else row_eval<2, U, R>(P, W, L, d, G, o);
 }
 
 // Sum over the 64 lanes of a wave with DPP moves (no LDS round trips):
@@ -745,7 +751,7 @@ __device__ __forceinline__ double subwave_sum(double v, unsigned S) {
 
 // sweep one block: 64 groups set up at a time, each group owns a sub-wave of
 // S lanes, lane row index r = tile*S + (lane mod S) fixed across groups
-template <bool MOVE>
+template <bool MOVE, class R>
 __device__ void sweep_block(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, int lane, const Block &b,
                             uint32_t wid, uint32_t step, bool dy, Acc &a) {
     GroupInfo &mg = L.G[lane];
@@ -784,7 +790,7 @@ __device__ void sweep_block(const DevProblem &P, const WalkerCtx &W, const WaveL
                     double v = 0.0;
                     if (rv) {
                         RowRes o;
-                        row_eval_any<true>(P, W, L, vp, d, gv, o);
+                        row_eval_any<true, R>(P, W, L, vp, d, gv, o);
                         if (o.ok) {
                             a.E += o.hnm * o.psi;
                             v = fabs(o.psi);
@@ -809,7 +815,7 @@ __device__ void sweep_block(const DevProblem &P, const WalkerCtx &W, const WaveL
                 if (rv && gc < nlive) {
                     RowRes o;
                     GroupView gv = group_view<false>(L, gi);
-                    row_eval_any<false>(P, W, L, vp, d, gv, o);
+                    row_eval_any<false, R>(P, W, L, vp, d, gv, o);
                     if (o.ok) {
                         a.E += o.hnm * o.psi;
                         v = fabs(o.psi);
@@ -835,7 +841,7 @@ __device__ void sweep_block(const DevProblem &P, const WalkerCtx &W, const WaveL
     }
 }
 
-template <bool MOVE>
+template <bool MOVE, class R>
 __device__ void walker_eval(const DevProblem &P, const WaveLDS &L, int lane, unsigned long long key, unsigned virt,
                             double psin, uint32_t wid, uint32_t step, EvalOut &out) {
     WalkerCtx W;
@@ -863,7 +869,7 @@ __device__ void walker_eval(const DevProblem &P, const WaveLDS &L, int lane, uns
             Block b;
             if (!block_setup(P, W, rk, pk, b)) continue;
             if (P.active_only && b.vp[0] + b.vp[1] > 0) continue;
-            sweep_block<MOVE>(P, W, L, lane, b, wid, step, dy, a);
+            sweep_block<MOVE, R>(P, W, L, lane, b, wid, step, dy, a);
         }
     double E = wave_sum(a.E), G = wave_sum(a.G);
     double D = dy ? wave_sum(a.D) : 0.0;
@@ -897,7 +903,7 @@ __device__ void walker_eval(const DevProblem &P, const WaveLDS &L, int lane, uns
         RowDec d;
         row_decode(P, W, b, r, d);
         RowRes o;
-        row_eval_any<true>(P, W, L, vp, d, sgv, o);
+        row_eval_any<true, R>(P, W, L, vp, d, sgv, o);
         if (!o.ok || o.psi == 0.0) continue;
         double tau = exp_draw(P.seed, wid, step, 1u, (uint32_t)d.cls, 0u) / fabs(o.psi);
         if (tau < b2 || (tau == b2 && d.cls < bcls)) {
@@ -973,6 +979,7 @@ __device__ __forceinline__ long long class_of_virt(const DevProblem &P, unsigned
     return class_id2(P.V, (int)v0, (int)v1);
 }
 
+template <class R>
 __global__ __launch_bounds__(64 * WPB, 4) void k_sample(DevProblem P, WalkerArrays S, long long W, long long step0,
                                                    int nsteps, long long burn_in, int NL) {
     extern __shared__ unsigned char smem[];
@@ -990,8 +997,15 @@ __global__ __launch_bounds__(64 * WPB, 4) void k_sample(DevProblem P, WalkerArra
         EvalOut o;
         key = uni(key);
         virt = uni(virt);
+        if constexpr (sizeof(R) < sizeof(double)) {
+            // precision form: the walker's own overlap, which divides every
+            // term of E_L, is recomputed in FP64 (one lane, once per step)
+            double pd = 0.0;
+            if (lane == 0) pd = psi_direct<double>(P, key, virt);
+            psi = __shfl(pd, 0);
+        }
         psi = uni(psi);
-        walker_eval<true>(P, L, lane, key, virt, psi, (uint32_t)w, (uint32_t)step, o);
+        walker_eval<true, R>(P, L, lane, key, virt, psi, (uint32_t)w, (uint32_t)step, o);
         bool good = o.moved && isfinite(o.eloc) && o.gamma > 0.0 && isfinite(o.gamma);
         if (!good) { nbad++; continue; }
         if (step >= burn_in) {
@@ -1024,6 +1038,7 @@ __global__ __launch_bounds__(64 * WPB, 4) void k_sample(DevProblem P, WalkerArra
 }
 
 // local energies without moving (parity / snapshots)
+template <class R>
 __global__ __launch_bounds__(64 * WPB, 4) void k_eval(DevProblem P, const unsigned long long *keys, const unsigned *virts,
                                                  const int *valid, long long n, int NL, double *eloc, double *psi_out,
                                                  double *gamma, double *elocd, int *cls_out) {
@@ -1036,11 +1051,12 @@ __global__ __launch_bounds__(64 * WPB, 4) void k_eval(DevProblem P, const unsign
     unsigned virt = virts[i];
     int nv = ((virt & 0xFFFFu) != SCQ_NOVIRT) + ((virt >> 16) != SCQ_NOVIRT);
     double ps = 0.0;
-    if (lane == 0 && valid[i]) ps = psi_direct(P, key, virt);
+    // psi(n) itself in FP64 in both forms: it divides every term of E_L
+    if (lane == 0 && valid[i]) ps = psi_direct<double>(P, key, virt);
     ps = __shfl(ps, 0);
     EvalOut o;
     if (ps != 0.0) {
-        walker_eval<false>(P, L, lane, key, virt, ps, (uint32_t)i, 0u, o);
+        walker_eval<false, R>(P, L, lane, key, virt, ps, (uint32_t)i, 0u, o);
     } else {
         o.eloc = o.elocd = o.gamma = NAN;
     }
@@ -1054,10 +1070,11 @@ __global__ __launch_bounds__(64 * WPB, 4) void k_eval(DevProblem P, const unsign
 }
 
 // psi of walkers (initialisation)
+template <class R>
 __global__ void k_psi(DevProblem P, const unsigned long long *keys, const unsigned *virts, long long n, double *psi) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    psi[i] = psi_direct(P, keys[i], virts[i]);
+    psi[i] = psi_direct<double>(P, keys[i], virts[i]);
 }
 
 // neighbour list of one walker (debug): one wave, groups and rows one lane at a time
@@ -1086,7 +1103,7 @@ __global__ __launch_bounds__(64) void k_neighbors(DevProblem P, unsigned long lo
                         row_decode(P, W, b, r, d);
                         RowRes o;
                         GroupView gv = group_view<false>(L, lane);
-                        row_eval_any<false>(P, W, L, vp, d, gv, o);
+                        row_eval_any<false, double>(P, W, L, vp, d, gv, o);
                         if (!o.ok) continue;
                         unsigned long long pos = atomicAdd(count, 1ull);
                         if ((long long)pos < cap) {

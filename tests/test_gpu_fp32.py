@@ -1,0 +1,95 @@
+"""The precision form (FP32 off-diagonal Slater-Condon and overlap terms from
+FP32 copies of the integrals, every sum, H_nn, psi(n), the accumulators and
+the estimators in FP64) against the FP64 oracle.
+
+Bar, derived from the arithmetic: a term's FP32 rounding is at most about
+2^-24 of its size, so |E_L(fp32) - E_L| <= 2^-24 (S_abs + |E_L| kappa) with
+S_abs the sum of the magnitudes of the terms of E_L and kappa the condition
+number of psi(n) (the oracle reports both).  The typical error is also
+checked against 1e-6 Eh (median), and the walk's estimators must agree with
+the exact values and with the FP64 walk well inside the statistical error.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import brute
+import oracle as O
+from helpers import cfg1_problem, sample_by_class
+from paper_1909_06935_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _engine(prob, precision, **kw):
+    from paper_1909_06935_amd.scqmc import Engine
+    e = Engine.from_problem(prob, **kw)
+    e.set_options(mode=kw.get("mode", 0), precision=precision, burn_in=kw.get("burn_in", 0),
+                  block_len=kw.get("block_len", 0))
+    return e
+
+
+def _check(prob, dets, label, median_bar=1e-6):
+    orc = O.Oracle.from_problem(prob, mode=1)
+    ref = orc.eval(dets, nthreads=8)
+    g = {k: v.cpu().numpy() for k, v in _engine(prob, 1, mode=1).eval_snapshot(dets).items()}
+    ok = ref["psi"] != 0
+    # psi(n) is evaluated in FP64 in both forms
+    scale = np.abs(ref["psi"]).max()
+    assert np.all(np.abs(g["psi"] - ref["psi"]) <= 1e-12 * scale), label
+    err = np.abs(g["eloc"] - ref["eloc"])[ok]
+    bound = U32 * (ref["sabs"] + np.abs(ref["eloc"]) * ref["kappa"])[ok] + 1e-12
+    assert np.all(err <= bound), (label, np.max(err / bound))
+    okd = ok & ~np.isnan(ref["eloc_d"])
+    errd = np.abs(g["eloc_d"] - ref["eloc_d"])[okd]
+    boundd = U32 * (ref["sabs"] + np.abs(ref["eloc_d"]) * ref["kappa"])[okd] + 1e-12
+    assert np.all(errd <= boundd), label
+    # determinants whose psi(n) is itself a cancelling sum (kappa = A(n)/|psi(n)|
+    # large, down to rounding noise) have an ill-defined E_L in any precision;
+    # the typical error is stated over the well-conditioned ones
+    wc = ref["kappa"][ok] < 1e4
+    med = float(np.median(err[wc]))
+    _say(f"{label}: {ok.sum()} dets ({wc.sum()} with kappa < 1e4), |dE_L| median {med:.2e}, "
+         f"p90 {np.quantile(err[wc], 0.9):.2e}, max {err[wc].max():.2e}, above 1e-6: {(err[wc] > 1e-6).sum()}")
+    assert med <= median_bar, (label, med)
+
+
+def test_fp32_eval_cfg1_all_determinants():
+    prob = cfg1_problem()
+    b = brute.allowed_space(prob.space)
+    _check(prob, np.array([brute.int_to_det(prob.space, x) for x in b]), "cfg1 fp32")
+
+
+def test_fp32_eval_cfg2_snapshot():
+    prob = wl.make_problem("cfg2")
+    prob.eps_virt = np.linspace(1.0, 3.0, prob.space.n_virt)
+    prob.e0_ref = float(np.load(wl.reference_file("cfg2"))["e_cas"])
+    orc = O.Oracle.from_problem(prob, mode=1)
+    _check(prob, sample_by_class(orc, prob.space, prob.ref_dets, 12, 2024), "cfg2 fp32")
+
+
+def test_fp32_walk_statistics_cfg1():
+    prob = cfg1_problem()
+    _say("cfg1 fp32 walk")
+    bf = brute.Brute(prob, wl.dense_eri(prob.chol), eps_virt=prob.eps_virt)
+    w0 = wl.draw_walkers(prob.ref_dets, prob.ref_coeff, 256, prob.seed_walk)
+    est = {}
+    for prec in (0, 1):
+        e = _engine(prob, prec, mode=1, burn_in=100, block_len=50)
+        e.init_walkers(w0, prob.seed_walk)
+        e.sample(1100)
+        est[prec] = e.read_estimates()
+    f32, f64 = est[1], est[0]
+    assert abs(f32["e_var"] - bf.e_var) < 5 * f32["e_var_err"]
+    assert abs(f32["e2"] - bf.e2) < 6 * f32["e2_err"]
+    # same chain up to rounding: the two forms agree far inside the error bar
+    assert abs(f32["e_var"] - f64["e_var"]) < 1e-3 * f64["e_var_err"], (f32, f64)
+    assert abs(f32["e2"] - f64["e2"]) < 1e-3 * f64["e2_err"], (f32, f64)
