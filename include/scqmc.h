@@ -96,6 +96,20 @@ typedef struct {
     int64_t n_steps_accumulated, n_walkers;
 } scqmc_estimates;
 
+/* Stochastic optimisation of the SC coefficients ("SC-MRCI(s)": AMSGrad on
+ * the sampled energy gradient).  With rho the walk's distribution,
+ *   g_l = < [class(n) = l] (E_L(n) - E) >_rho / c_l
+ * (the derivative overlap <n|psi_l>/<n|psi> is [class(n) = l]/c_l), which
+ * needs only the per-class sums of t and t*E_L the walk accumulates.  c0 is
+ * held fixed (the energy does not depend on the overall scale); classes with
+ * c_l = 0 stay at 0.  AMSGrad (Reddi, Kale, Kumar 2018): m <- b1 m + (1-b1) g,
+ * v <- b2 v + (1-b2) g^2, vmax <- max(vmax, v), c <- c - lr m/(sqrt(vmax)+eps). */
+typedef struct {
+    double lr, beta1, beta2, eps;
+    int64_t steps_per_iter;     /* walk steps whose samples make one gradient */
+    int64_t equil_steps;        /* steps walked, not sampled, after each update */
+} scqmc_amsgrad;
+
 /* Create a context on HIP device `device`.  hip_stream: a hipStream_t to
  * enqueue on, or NULL for a stream the context creates and owns. */
 scqmc_status scqmc_create(int device, void *hip_stream, scqmc_ctx **out);
@@ -196,6 +210,21 @@ scqmc_status scqmc_read_walkers(scqmc_ctx *ctx, uint64_t *dets, double *psi, int
 /* Steps taken since init_walkers and the count of walker-steps whose rates
  * summed to zero or whose local energy was not finite. */
 scqmc_status scqmc_read_counters(scqmc_ctx *ctx, int64_t *steps, int64_t *bad_steps);
+
+/* n_iter AMSGrad iterations on the placed walkers: per iteration the walkers'
+ * psi(n) is recomputed with the current coefficients, equil_steps steps are
+ * walked, the class sums are cleared, steps_per_iter steps are sampled, the
+ * energy and gradient are formed on the host and the coefficients updated.
+ * The moment estimates persist across calls (reset by set_sc_coeffs).
+ * Optional outputs: e_trace[n_iter] (sampled E of each iteration),
+ * g_trace[n_iter] (gradient 2-norm).  Synchronous.  Afterwards the walker and
+ * class sums hold the last iteration's samples and read_class_sums /
+ * set_sc_coeffs see the optimised coefficients (read them with
+ * scqmc_read_sc_coeffs). */
+scqmc_status scqmc_optimize(scqmc_ctx *ctx, const scqmc_amsgrad *opt, int64_t n_iter, double *e_trace,
+                            double *g_trace);
+/* Current SC coefficients: *c0 and c_cls[n], n = n_classes - 1. */
+scqmc_status scqmc_read_sc_coeffs(scqmc_ctx *ctx, double *c0, double *c_cls, int64_t n);
 
 /* Parity / debug.  Local energies of n determinants d_dets [n][2][words]
  * (device) without moving: E_L, psi, Gamma = sum_m |psi(m)/psi(n)|, the Dyall

@@ -73,6 +73,7 @@ struct scqmc_ctx {
     // walkers
     long long W = 0, step = 0;
     long long ncg = 0;   // walker groups with their own class sums (jackknife of E^(2))
+    std::vector<double> am_m, am_v, am_vmax;   // AMSGrad moments (classes 1..n_classes-1)
     unsigned long long seed = 0;
     DBuf wkey, wvirt, wpsi, wsum, cacc, bad;
     // snapshot scratch
@@ -468,6 +469,9 @@ scqmc_status scqmc_set_sc_coeffs(scqmc_ctx *c, double c0, const double *c_cls, i
     c->ccls_h.assign(c->ncls, 0.0);
     c->ccls_h[0] = c0;
     for (long long i = 0; i < n; i++) c->ccls_h[i + 1] = c_cls[i];
+    c->am_m.clear();
+    c->am_v.clear();
+    c->am_vmax.clear();
     HIPCHK(c, hipSetDevice(c->device));
     TRY(dalloc(c, c->ccls, sizeof(double) * c->ncls));
     HIPCHK(c, hipMemcpyAsync(c->ccls.p, c->ccls_h.data(), sizeof(double) * c->ncls, hipMemcpyHostToDevice, c->stream));
@@ -1160,6 +1164,116 @@ scqmc_status scqmc_load_state(scqmc_ctx *c, const void *buf, int64_t len) {
     c->step = hdr[9];
     c->seed = (unsigned long long)hdr[10];
     c->has_walkers = true;
+    return SCQMC_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// SC coefficient optimisation ("SC-MRCI(s)"): AMSGrad on the sampled gradient
+// ---------------------------------------------------------------------------
+static scqmc_status launch_sample(scqmc_ctx *c, long long n_steps, long long burn_in) {
+    DevProblem P = dev_problem(c);
+    WalkerArrays S;
+    S.key = c->wkey.as<unsigned long long>();
+    S.virt = c->wvirt.as<unsigned>();
+    S.psi = c->wpsi.as<double>();
+    S.wsum = c->wsum.as<double>();
+    S.cacc = c->cacc.as<unsigned long long>();
+    S.ncg = (int)c->ncg;
+    S.bad = c->bad.as<unsigned long long>();
+    int NL = lists_per_group(c);
+    size_t lds = kernel_lds(c);
+    long long blk = c->opt.block_len > 0 ? c->opt.block_len : 1;
+    for (long long done = 0; done < n_steps; done += blk) {
+        int ns = (int)std::min(blk, n_steps - done);
+        if (c->opt.precision == 1)
+            hipLaunchKernelGGL(k_sample<float>, dim3(grid1(c->W, WPB)), dim3(64 * WPB), lds, c->stream, P, S, c->W,
+                               c->step + done, ns, burn_in, NL);
+        else
+            hipLaunchKernelGGL(k_sample<double>, dim3(grid1(c->W, WPB)), dim3(64 * WPB), lds, c->stream, P, S, c->W,
+                               c->step + done, ns, burn_in, NL);
+        HIPCHK(c, hipGetLastError());
+    }
+    c->step += n_steps;
+    return SCQMC_OK;
+}
+
+static scqmc_status refresh_psi(scqmc_ctx *c) {
+    DevProblem P = dev_problem(c);
+    long long W = c->W;
+    if (c->opt.precision == 1)
+        hipLaunchKernelGGL(k_psi<float>, dim3(grid1(W, 64)), dim3(64), 0, c->stream, P,
+                           c->wkey.as<unsigned long long>(), c->wvirt.as<unsigned>(), W, c->wpsi.as<double>());
+    else
+        hipLaunchKernelGGL(k_psi<double>, dim3(grid1(W, 64)), dim3(64), 0, c->stream, P,
+                           c->wkey.as<unsigned long long>(), c->wvirt.as<unsigned>(), W, c->wpsi.as<double>());
+    HIPCHK(c, hipGetLastError());
+    std::vector<double> psi(W);
+    HIPCHK(c, hipMemcpyAsync(psi.data(), c->wpsi.p, sizeof(double) * W, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (long long i = 0; i < W; i++)
+        if (!(std::isfinite(psi[i]) && psi[i] != 0.0))
+            FAIL(c, SCQMC_E_NUMERIC, "walker " + std::to_string(i) + " has psi = 0 or non-finite after an update");
+    return SCQMC_OK;
+}
+
+scqmc_status scqmc_optimize(scqmc_ctx *c, const scqmc_amsgrad *o, int64_t n_iter, double *e_trace, double *g_trace) {
+    if (!c || !o) return SCQMC_E_INVALID_ARG;
+    if (!c->has_walkers) FAIL(c, SCQMC_E_STATE, "init_walkers first");
+    if (c->opt.mode == 1 && !c->has_dyall) FAIL(c, SCQMC_E_STATE, "mode 1 needs set_dyall");
+    if (n_iter < 0 || o->steps_per_iter <= 0 || o->equil_steps < 0 || !(o->lr > 0) || !(o->eps > 0) ||
+        !(o->beta1 >= 0 && o->beta1 < 1) || !(o->beta2 >= 0 && o->beta2 < 1))
+        FAIL(c, SCQMC_E_INVALID_ARG, "bad AMSGrad parameters");
+    long long need = (long long)n_iter * (o->steps_per_iter + o->equil_steps);
+    if (c->step + need >= (1LL << 31)) FAIL(c, SCQMC_E_UNSUPPORTED, "step counter limit (2^31) reached");
+    HIPCHK(c, hipSetDevice(c->device));
+    TRY(ensure_f32(c));
+    long long n = c->ncls;
+    if ((long long)c->am_m.size() != n) {
+        c->am_m.assign(n, 0.0);
+        c->am_v.assign(n, 0.0);
+        c->am_vmax.assign(n, 0.0);
+    }
+    const long long never = (1LL << 62);
+    for (long long it = 0; it < n_iter; it++) {
+        TRY(refresh_psi(c));
+        if (o->equil_steps > 0) TRY(launch_sample(c, o->equil_steps, never));
+        HIPCHK(c, hipMemsetAsync(c->wsum.p, 0, sizeof(double) * 3 * c->W, c->stream));
+        HIPCHK(c, hipMemsetAsync(c->cacc.p, 0, class_acc_bytes(c), c->stream));
+        TRY(launch_sample(c, o->steps_per_iter, 0));
+        std::vector<double> ws, cs;
+        TRY(download_sums(c, ws, cs));
+        double St = 0, Ste = 0;
+        for (long long l = 0; l < n; l++) { St += cs[l]; Ste += cs[n + l]; }
+        if (!(St > 0)) FAIL(c, SCQMC_E_NUMERIC, "no residence time sampled");
+        double E = Ste / St, g2 = 0;
+        for (long long l = 1; l < n; l++) {
+            double cl = c->ccls_h[l];
+            if (cl == 0.0) continue;
+            double g = (cs[n + l] - E * cs[l]) / (cl * St);
+            g2 += g * g;
+            double &m = c->am_m[l], &v = c->am_v[l], &vm = c->am_vmax[l];
+            m = o->beta1 * m + (1 - o->beta1) * g;
+            v = o->beta2 * v + (1 - o->beta2) * g * g;
+            vm = std::max(vm, v);
+            c->ccls_h[l] = cl - o->lr * m / (std::sqrt(vm) + o->eps);
+            if (c->ccls_h[l] == 0.0) c->ccls_h[l] = cl;   // a class never gets switched off
+        }
+        if (!all_finite(c->ccls_h.data(), n)) FAIL(c, SCQMC_E_NUMERIC, "non-finite coefficient after an update");
+        HIPCHK(c, hipMemcpyAsync(c->ccls.p, c->ccls_h.data(), sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+        if (e_trace) e_trace[it] = E;
+        if (g_trace) g_trace[it] = std::sqrt(g2);
+    }
+    TRY(refresh_psi(c));
+    return SCQMC_OK;
+}
+
+scqmc_status scqmc_read_sc_coeffs(scqmc_ctx *c, double *c0, double *c_cls, int64_t n) {
+    if (!c) return SCQMC_E_INVALID_ARG;
+    if (!c->has_coef) FAIL(c, SCQMC_E_STATE, "set_sc_coeffs first");
+    if (n != c->ncls - 1) FAIL(c, SCQMC_E_INVALID_ARG, "n must equal n_classes - 1");
+    if (c0) *c0 = c->ccls_h[0];
+    if (c_cls) for (long long i = 0; i < n; i++) c_cls[i] = c->ccls_h[i + 1];
     return SCQMC_OK;
 }
 

@@ -47,6 +47,11 @@ class Estimates(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class AMSGrad(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
+                ("steps_per_iter", C.c_int64), ("equil_steps", C.c_int64)]
+
+
 _lib = None
 
 
@@ -95,6 +100,8 @@ def lib():
             "scqmc_debug_neighbors": ([P, P, i64, P, P, P, P, C.POINTER(i64)], C.c_int),
             "scqmc_save_state": ([P, P, i64, C.POINTER(i64)], C.c_int),
             "scqmc_load_state": ([P, P, i64], C.c_int),
+            "scqmc_optimize": ([P, C.POINTER(AMSGrad), i64, P, P], C.c_int),
+            "scqmc_read_sc_coeffs": ([P, P, P, i64], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -177,6 +184,20 @@ class Engine:
     def set_dyall(self, eps_virt, e0):
         eps_virt = _c64(eps_virt)
         self._check(lib().scqmc_set_dyall(self.h, _p(eps_virt), float(e0)))
+
+    def optimize(self, n_iter, lr=0.01, beta1=0.9, beta2=0.999, eps=1e-8, steps_per_iter=50, equil_steps=10):
+        """AMSGrad iterations on the SC coefficients; returns (energy trace, gradient-norm trace)."""
+        o = AMSGrad(float(lr), float(beta1), float(beta2), float(eps), int(steps_per_iter), int(equil_steps))
+        e = np.zeros(max(int(n_iter), 1))
+        g = np.zeros(max(int(n_iter), 1))
+        self._check(lib().scqmc_optimize(self.h, C.byref(o), int(n_iter), _p(e), _p(g)))
+        return e[:n_iter], g[:n_iter]
+
+    def read_sc_coeffs(self):
+        c0 = C.c_double()
+        c = np.zeros(max(self.n_classes - 1, 1))
+        self._check(lib().scqmc_read_sc_coeffs(self.h, C.byref(c0), _p(c), self.n_classes - 1))
+        return c0.value, c[:self.n_classes - 1]
 
     def reference_energy(self):
         e = C.c_double()

@@ -301,3 +301,23 @@ def rdm1_active(space, basis, phi0):
                     if i is not None:
                         g[t, u] += phi0[i] * s1 * s2 * phi0[j]
     return g / float(phi0 @ phi0)
+
+
+def sc_eigen(b):
+    """Strongly contracted eigenproblem over the basis of a Brute instance:
+    contracted states psi_0 = phi0 and psi_l = P_l H phi0 (classes with a
+    nonzero projection); H_kl = <psi_k|H|psi_l>, S_kl = <psi_k|psi_l>
+    (diagonal: classes are disjoint).  Returns (lowest eigenvalue, class ids,
+    coefficients scaled so that the class-0 coefficient is 1)."""
+    cls = b.cls
+    ids = [0] + [int(l) for l in np.unique(cls) if l != 0 and np.any(b.hphi[cls == l] != 0)]
+    Psi = np.zeros((len(b.basis), len(ids)))
+    Psi[:, 0] = b.phi0
+    for k, l in enumerate(ids[1:], start=1):
+        Psi[:, k] = np.where(cls == l, b.hphi, 0.0)
+    Hs = Psi.T @ b.H @ Psi
+    Ss = Psi.T @ Psi
+    d = 1.0 / np.sqrt(np.diag(Ss))
+    w, U = np.linalg.eigh(d[:, None] * Hs * d[None, :])
+    c = d * U[:, 0]
+    return float(w[0]), ids, c / c[0]

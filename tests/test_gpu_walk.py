@@ -158,3 +158,30 @@ def test_error_paths():
     blob = e2.save_state()
     assert status_of(lambda: e.load_state(blob)) == E_INVALID_ARG
     assert status_of(lambda: e.load_state(blob[:50])) == E_INVALID_ARG
+
+
+def test_sc_coefficient_optimisation_cfg1():
+    """AMSGrad on the sampled gradient moves the coefficients towards the
+    strongly contracted optimum: the exact energy of the final coefficients
+    recovers most of the gap between the starting energy and E_SC, never goes
+    below E_SC, and the sampled energies track the exact ones."""
+    prob = cfg1_problem()
+    _say("cfg1 optimisation")
+    eri = wl.dense_eri(prob.chol)
+    b0 = brute.Brute(prob, eri)
+    esc, ids, _ = brute.sc_eigen(b0)
+    eng = _engine(prob, mode=0, burn_in=0, block_len=25)
+    eng.init_walkers(wl.draw_walkers(prob.ref_dets, prob.ref_coeff, 256, prob.seed_walk), prob.seed_walk)
+    eng.sample(50)
+    e_tr, g_tr = eng.optimize(400, lr=0.02, steps_per_iter=40, equil_steps=10)
+    assert np.all(np.isfinite(e_tr)) and np.all(np.isfinite(g_tr))
+    c0, c = eng.read_sc_coeffs()
+    assert c0 == prob.c0
+    p2 = wl.Problem(**{**prob.__dict__})
+    p2.c_cls = c
+    e_final = brute.Brute(p2, eri).e_var
+    _say(f"E start {b0.e_var:.6f}  E final (exact) {e_final:.6f}  E_SC {esc:.6f}  last sampled {e_tr[-20:].mean():.6f}")
+    assert e_final >= esc - 1e-9
+    assert e_final - esc <= 0.01 * (b0.e_var - esc), (e_final, esc, b0.e_var)
+    # the sampled energies of the last iterations scatter around the exact value
+    assert abs(e_tr[-50:].mean() - e_final) < 0.05 * (b0.e_var - esc)
