@@ -130,7 +130,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=300)
-    ap.add_argument("--config", default="cfg2", choices=["cfg2", "cfg3"])
+    ap.add_argument("--config", default="cfg2", choices=["cfg2", "cfg3", "batch"])
     ap.add_argument("--walkers", type=int, default=0)
     ap.add_argument("--block", type=int, default=1, help="steps per kernel launch")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
@@ -153,6 +153,10 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is described, "
               "not launched, in this build", file=sys.stderr)
         sys.exit(2)
+
+    if args.config == "batch":
+        run_batch(args)
+        return
 
     import torch
     from paper_1909_06935_amd import workloads as wl
@@ -228,6 +232,52 @@ def main():
                      "flops_per_walker_step": per_flops},
         }
         out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
+
+
+def run_batch(args):
+    """Batched form: 64 systems of uneven sizes (CAS(4,4)..CAS(12,12), 20-80
+    orbitals, 100-20k-determinant references, 256-8192 walkers) walked by one
+    launch per group of steps, against the same systems walked one after the
+    other with the plain kernel.  Both take the same steps of the same chains
+    (bit-identical results), so they compare at equal statistical error."""
+    import torch
+    from paper_1909_06935_amd import workloads as wl
+    from paper_1909_06935_amd.scqmc import Batch, Engine
+    systems = wl.make_batch_systems(64)
+    engines = []
+    for p in systems:
+        p.eps_virt = np.linspace(1.0, 3.0, p.space.n_virt)
+        p.e0_ref = 0.0
+        e = Engine.from_problem(p, mode=1, burn_in=0, block_len=0)
+        e.set_dyall(p.eps_virt, e.reference_energy())
+        e.init_walkers(wl.draw_walkers(p.ref_dets, p.ref_coeff, p.n_walkers, p.seed_walk), p.seed_walk)
+        engines.append(e)
+    print(f"# batch: {len(engines)} systems, {sum(p.n_walkers for p in systems)} walkers", file=sys.stderr, flush=True)
+    b = Batch(engines)
+    b.sample(args.warmup)
+    order, spl, _ = b.tune(4)
+    K = args.steps
+    t0 = time.perf_counter()
+    for e in engines:
+        e.sample(K)
+    for e in engines:
+        e.synchronize()
+    serial = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    b.sample(K)
+    batched = time.perf_counter() - t0
+    ws = sum(p.n_walkers for p in systems) * K
+    out = {
+        "metric": "walker-steps/s (batched form, 64 systems)", "value": ws / batched, "unit": "walker-steps/s",
+        "n_gpus": 1, "steps": K, "warmup": args.warmup, "ms_per_step": 1e3 * batched / K, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "64 systems: CAS(4,4)-CAS(12,12), 20-80 orbitals, 100-20k-det synthetic SCI "
+                               "references, 256-8192 walkers each, SC-MRCI + SC-NEVPT2 mode",
+                   "walkers": sum(p.n_walkers for p in systems)},
+        "serial_plain_value": ws / serial, "speedup_vs_serial": serial / batched,
+        "schedule": {"order": order, "steps_per_launch": spl},
+    }
     print(json.dumps(out), flush=True)
 
 

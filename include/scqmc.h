@@ -245,6 +245,33 @@ scqmc_status scqmc_debug_neighbors(scqmc_ctx *ctx, const uint64_t *det, int64_t 
 scqmc_status scqmc_save_state(scqmc_ctx *ctx, void *buf, int64_t cap, int64_t *used);
 scqmc_status scqmc_load_state(scqmc_ctx *ctx, const void *buf, int64_t len);
 
+/* ------------------------------------------------------------------------
+ * Batched form: several contexts (independent systems of any sizes, each with
+ * placed walkers, all on one device and in one precision) walked by one
+ * launch per group of steps.  A schedule maps workgroups to (system, walker);
+ * a walker's chain depends only on its own id and its system's step counter,
+ * so the results equal those of the systems walked one by one, bit for bit.
+ * The launch and the step advance are captured in a HIP graph and replayed.
+ * The batch keeps pointers to the contexts (which must outlive it) and reads
+ * their current state at every call.
+ * ------------------------------------------------------------------------ */
+typedef struct scqmc_batch scqmc_batch;
+
+scqmc_status scqmc_batch_create(scqmc_ctx *const *ctxs, int32_t n, scqmc_batch **out);
+void scqmc_batch_destroy(scqmc_batch *batch);
+const char *scqmc_batch_last_error(const scqmc_batch *batch);
+/* n_steps steps of every system (synchronous); each context's step counter
+ * advances by n_steps. */
+scqmc_status scqmc_batch_sample(scqmc_batch *batch, int64_t n_steps);
+/* Schedule: order 0 = systems one after another, 1 = walkers of all systems
+ * interleaved, 2 = costliest systems first; steps_per_launch 1..1024. */
+scqmc_status scqmc_batch_set_schedule(scqmc_batch *batch, int32_t order, int32_t steps_per_launch);
+/* Autotuner: times trial_steps steps (real steps of every system) for each
+ * order 0..2 and 1, 2, 4 steps per launch and keeps the fastest; outputs the
+ * choice and its time per step (each optional). */
+scqmc_status scqmc_batch_tune(scqmc_batch *batch, int64_t trial_steps, int32_t *order, int32_t *steps_per_launch,
+                              double *ms_per_step);
+
 #ifdef __cplusplus
 }
 #endif

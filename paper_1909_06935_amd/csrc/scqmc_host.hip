@@ -13,6 +13,7 @@
 #include <new>
 #include <string>
 #include <vector>
+#include <chrono>
 
 #include "../../include/scqmc.h"
 #include "scqmc_setup.hip"
@@ -1274,6 +1275,282 @@ scqmc_status scqmc_read_sc_coeffs(scqmc_ctx *c, double *c0, double *c_cls, int64
     if (n != c->ncls - 1) FAIL(c, SCQMC_E_INVALID_ARG, "n must equal n_classes - 1");
     if (c0) *c0 = c->ccls_h[0];
     if (c_cls) for (long long i = 0; i < n; i++) c_cls[i] = c->ccls_h[i + 1];
+    return SCQMC_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Batched form: several contexts (systems) walked by one launch
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct scqmc_batch {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    std::vector<scqmc_ctx *> ctx;
+    int precision = 0;
+    int order = 0;          // 0: system by system, 1: walkers interleaved, 2: costliest systems first
+    int spl = 1;            // steps per launch
+    long long nslots = 0;
+    std::vector<long long> Ws;
+    int sched_order = -1;
+    DBuf dsys, dslot_sys, dslot_w;
+    size_t lds = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int graph_spl = 0;
+    long long graph_slots = -1;
+};
+
+namespace {
+#define BFAIL(b, code, msg)        \
+    do {                           \
+        (b)->err = (msg);          \
+        return (code);             \
+    } while (0)
+#define BHIP(b, call)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            (b)->err = std::string(#call) + ": " + hipGetErrorString(e_);              \
+            return e_ == hipErrorOutOfMemory ? SCQMC_E_OOM : SCQMC_E_DEVICE;           \
+        }                                                                              \
+    } while (0)
+
+// relative cost of one walker-step of a system: neighbours ~ (electrons x
+// orbitals)^2 of the non-core space
+double batch_cost(const scqmc_ctx *c) {
+    double e = c->nea + c->neb, o = 2.0 * c->Np;
+    return e * e * o * o;
+}
+
+void free_graph(scqmc_batch *b) {
+    if (b->gexec) hipGraphExecDestroy(b->gexec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+    b->graph_spl = 0;
+}
+
+scqmc_status batch_schedule(scqmc_batch *b) {
+    int n = (int)b->ctx.size();
+    std::vector<long long> Ws(n);
+    long long tot = 0;
+    for (int i = 0; i < n; i++) { Ws[i] = b->ctx[i]->W; tot += Ws[i]; }
+    if (Ws == b->Ws && b->sched_order == b->order) return SCQMC_OK;
+    if (tot >= (1LL << 31)) BFAIL(b, SCQMC_E_UNSUPPORTED, "too many walkers in one batch");
+    std::vector<int> ss, ww;
+    ss.reserve(tot);
+    ww.reserve(tot);
+    std::vector<int> sys_order(n);
+    for (int i = 0; i < n; i++) sys_order[i] = i;
+    if (b->order == 2)
+        std::stable_sort(sys_order.begin(), sys_order.end(),
+                         [&](int x, int y) { return batch_cost(b->ctx[x]) > batch_cost(b->ctx[y]); });
+    if (b->order == 1) {
+        long long mx = *std::max_element(Ws.begin(), Ws.end());
+        for (long long w = 0; w < mx; w++)
+            for (int i = 0; i < n; i++)
+                if (w < Ws[i]) { ss.push_back(i); ww.push_back((int)w); }
+    } else {
+        for (int i : sys_order)
+            for (long long w = 0; w < Ws[i]; w++) { ss.push_back(i); ww.push_back((int)w); }
+    }
+    hipError_t e1 = hipSuccess;
+    b->dslot_sys.release();
+    b->dslot_w.release();
+    e1 = hipMalloc(&b->dslot_sys.p, sizeof(int) * tot);
+    if (e1 == hipSuccess) e1 = hipMalloc(&b->dslot_w.p, sizeof(int) * tot);
+    if (e1 != hipSuccess) BFAIL(b, SCQMC_E_OOM, "schedule arrays");
+    b->dslot_sys.n = b->dslot_w.n = sizeof(int) * tot;
+    BHIP(b, hipMemcpy(b->dslot_sys.p, ss.data(), sizeof(int) * tot, hipMemcpyHostToDevice));
+    BHIP(b, hipMemcpy(b->dslot_w.p, ww.data(), sizeof(int) * tot, hipMemcpyHostToDevice));
+    b->nslots = tot;
+    b->Ws = Ws;
+    b->sched_order = b->order;
+    free_graph(b);
+    return SCQMC_OK;
+}
+
+scqmc_status batch_upload(scqmc_batch *b) {
+    int n = (int)b->ctx.size();
+    std::vector<BatchSys> hs(n);
+    int NLmax = 1;
+    for (int i = 0; i < n; i++) {
+        scqmc_ctx *c = b->ctx[i];
+        if (!c->has_walkers) BFAIL(b, SCQMC_E_STATE, "context " + std::to_string(i) + " has no walkers");
+        if (c->opt.precision != b->precision) BFAIL(b, SCQMC_E_INVALID_ARG, "contexts differ in precision");
+        if (c->opt.mode == 1 && !c->has_dyall) BFAIL(b, SCQMC_E_STATE, "mode 1 needs set_dyall");
+        scqmc_status st = ensure_f32(c);
+        if (st != SCQMC_OK) BFAIL(b, st, c->err);
+        BatchSys &B = hs[i];
+        std::memset(&B, 0, sizeof(B));
+        B.P = dev_problem(c);
+        B.S.key = c->wkey.as<unsigned long long>();
+        B.S.virt = c->wvirt.as<unsigned>();
+        B.S.psi = c->wpsi.as<double>();
+        B.S.wsum = c->wsum.as<double>();
+        B.S.cacc = c->cacc.as<unsigned long long>();
+        B.S.ncg = (int)c->ncg;
+        B.S.bad = c->bad.as<unsigned long long>();
+        B.W = c->W;
+        B.step0 = c->step;
+        B.burn_in = c->opt.burn_in;
+        B.NL = lists_per_group(c);
+        NLmax = std::max(NLmax, B.NL);
+        if (c->step >= (1LL << 31) - (1LL << 20)) BFAIL(b, SCQMC_E_UNSUPPORTED, "step counter limit");
+    }
+    for (int i = 0; i < n; i++) BHIP(b, hipStreamSynchronize(b->ctx[i]->stream));
+    if (b->dsys.n < sizeof(BatchSys) * n) {
+        b->dsys.release();
+        if (hipMalloc(&b->dsys.p, sizeof(BatchSys) * n) != hipSuccess) BFAIL(b, SCQMC_E_OOM, "batch descriptors");
+        b->dsys.n = sizeof(BatchSys) * n;
+        free_graph(b);
+    }
+    BHIP(b, hipMemcpy(b->dsys.p, hs.data(), sizeof(BatchSys) * n, hipMemcpyHostToDevice));
+    b->lds = WPB * wave_lds_bytes(NLmax);
+    return SCQMC_OK;
+}
+
+scqmc_status batch_launch(scqmc_batch *b, int nsteps) {
+    int n = (int)b->ctx.size();
+    dim3 grid(grid1(b->nslots, WPB)), blk(64 * WPB);
+    if (b->precision == 1)
+        hipLaunchKernelGGL(k_sample_batch<float>, grid, blk, b->lds, b->stream, b->dsys.as<const BatchSys>(),
+                           b->dslot_sys.as<const int>(), b->dslot_w.as<const int>(), b->nslots, nsteps);
+    else
+        hipLaunchKernelGGL(k_sample_batch<double>, grid, blk, b->lds, b->stream, b->dsys.as<const BatchSys>(),
+                           b->dslot_sys.as<const int>(), b->dslot_w.as<const int>(), b->nslots, nsteps);
+    hipLaunchKernelGGL(k_batch_advance, dim3(grid1(n, 64)), dim3(64), 0, b->stream, b->dsys.as<BatchSys>(), n, nsteps);
+    BHIP(b, hipGetLastError());
+    return SCQMC_OK;
+}
+
+// one graph per (steps per launch, schedule): a batched launch and the step
+// advance, replayed as many times as needed
+scqmc_status batch_graph(scqmc_batch *b) {
+    if (b->gexec && b->graph_spl == b->spl && b->graph_slots == b->nslots) return SCQMC_OK;
+    free_graph(b);
+    BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    scqmc_status st = batch_launch(b, b->spl);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->stream, &g);
+    if (st != SCQMC_OK) { if (g) hipGraphDestroy(g); return st; }
+    if (e != hipSuccess) BFAIL(b, SCQMC_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    b->graph = g;
+    BHIP(b, hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
+    b->graph_spl = b->spl;
+    b->graph_slots = b->nslots;
+    return SCQMC_OK;
+}
+
+scqmc_status batch_run(scqmc_batch *b, long long n_steps) {
+    if (n_steps <= 0) return SCQMC_OK;
+    scqmc_status st = batch_schedule(b);
+    if (st != SCQMC_OK) return st;
+    st = batch_upload(b);
+    if (st != SCQMC_OK) return st;
+    long long full = n_steps / b->spl, rest = n_steps % b->spl;
+    if (full > 0) {
+        st = batch_graph(b);
+        if (st != SCQMC_OK) return st;
+        for (long long i = 0; i < full; i++) BHIP(b, hipGraphLaunch(b->gexec, b->stream));
+    }
+    if (rest > 0) {
+        st = batch_launch(b, (int)rest);
+        if (st != SCQMC_OK) return st;
+    }
+    BHIP(b, hipStreamSynchronize(b->stream));
+    for (scqmc_ctx *c : b->ctx) c->step += n_steps;
+    return SCQMC_OK;
+}
+}  // namespace
+
+extern "C" {
+
+scqmc_status scqmc_batch_create(scqmc_ctx *const *ctxs, int32_t n, scqmc_batch **out) {
+    if (!out || !ctxs || n <= 0) return SCQMC_E_INVALID_ARG;
+    *out = nullptr;
+    int dev = ctxs[0] ? ctxs[0]->device : 0;
+    for (int i = 0; i < n; i++) {
+        if (!ctxs[i]) return SCQMC_E_INVALID_ARG;
+        if (ctxs[i]->device != dev) return SCQMC_E_INVALID_ARG;
+        for (int j = 0; j < i; j++)
+            if (ctxs[j] == ctxs[i]) return SCQMC_E_INVALID_ARG;
+    }
+    scqmc_batch *b = new (std::nothrow) scqmc_batch();
+    if (!b) return SCQMC_E_OOM;
+    b->device = dev;
+    b->ctx.assign(ctxs, ctxs + n);
+    b->precision = ctxs[0]->opt.precision;
+    if (hipSetDevice(dev) != hipSuccess || hipStreamCreate(&b->stream) != hipSuccess) {
+        delete b;
+        return SCQMC_E_DEVICE;
+    }
+    *out = b;
+    return SCQMC_OK;
+}
+
+void scqmc_batch_destroy(scqmc_batch *b) {
+    if (!b) return;
+    hipSetDevice(b->device);
+    if (b->stream) hipStreamSynchronize(b->stream);
+    free_graph(b);
+    b->dsys.release();
+    b->dslot_sys.release();
+    b->dslot_w.release();
+    if (b->stream) hipStreamDestroy(b->stream);
+    delete b;
+}
+
+const char *scqmc_batch_last_error(const scqmc_batch *b) { return b ? b->err.c_str() : "null batch"; }
+
+scqmc_status scqmc_batch_sample(scqmc_batch *b, int64_t n_steps) {
+    if (!b) return SCQMC_E_INVALID_ARG;
+    if (n_steps < 0) BFAIL(b, SCQMC_E_INVALID_ARG, "negative n_steps");
+    BHIP(b, hipSetDevice(b->device));
+    b->precision = b->ctx[0]->opt.precision;
+    return batch_run(b, n_steps);
+}
+
+scqmc_status scqmc_batch_tune(scqmc_batch *b, int64_t trial_steps, int32_t *order, int32_t *steps_per_launch,
+                              double *ms_per_step) {
+    if (!b) return SCQMC_E_INVALID_ARG;
+    if (trial_steps <= 0) BFAIL(b, SCQMC_E_INVALID_ARG, "trial_steps must be positive");
+    BHIP(b, hipSetDevice(b->device));
+    b->precision = b->ctx[0]->opt.precision;
+    const int orders[3] = {0, 1, 2}, spls[3] = {1, 2, 4};
+    double best = 1e300;
+    int bo = 0, bs = 1;
+    for (int o : orders)
+        for (int sp : spls) {
+            b->order = o;
+            b->spl = sp;
+            long long nst = ((trial_steps + sp - 1) / sp) * sp;
+            // untimed first call builds the schedule and the graph
+            scqmc_status st = batch_run(b, sp);
+            if (st != SCQMC_OK) return st;
+            auto t0 = std::chrono::steady_clock::now();
+            st = batch_run(b, nst);
+            if (st != SCQMC_OK) return st;
+            double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / nst;
+            if (ms < best) { best = ms; bo = o; bs = sp; }
+        }
+    b->order = bo;
+    b->spl = bs;
+    if (order) *order = bo;
+    if (steps_per_launch) *steps_per_launch = bs;
+    if (ms_per_step) *ms_per_step = best;
+    return SCQMC_OK;
+}
+
+scqmc_status scqmc_batch_set_schedule(scqmc_batch *b, int32_t order, int32_t steps_per_launch) {
+    if (!b) return SCQMC_E_INVALID_ARG;
+    if (order < 0 || order > 2 || steps_per_launch < 1 || steps_per_launch > 1024)
+        BFAIL(b, SCQMC_E_INVALID_ARG, "order must be 0..2, steps_per_launch 1..1024");
+    b->order = order;
+    b->spl = steps_per_launch;
     return SCQMC_OK;
 }
 

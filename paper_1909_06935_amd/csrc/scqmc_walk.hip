@@ -979,14 +979,12 @@ __device__ __forceinline__ long long class_of_virt(const DevProblem &P, unsigned
     return class_id2(P.V, (int)v0, (int)v1);
 }
 
+// One walker's nsteps continuous-time steps: evaluate, accumulate after
+// burn-in, move.  Shared by the single-system and the batched launch.
 template <class R>
-__global__ __launch_bounds__(64 * WPB, 4) void k_sample(DevProblem P, WalkerArrays S, long long W, long long step0,
-                                                   int nsteps, long long burn_in, int NL) {
-    extern __shared__ unsigned char smem[];
-    int wave = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
-    long long w = (long long)blockIdx.x * WPB + wave;
-    if (w >= W) return;
-    WaveLDS L = carve(smem + wave * wave_lds_bytes(NL), NL);
+__device__ __forceinline__ void sample_walker(const DevProblem &P, const WalkerArrays &S, long long W, long long w,
+                                              long long step0, int nsteps, long long burn_in, const WaveLDS &L,
+                                              int lane) {
     unsigned long long key = S.key[w];
     unsigned virt = S.virt[w];
     double psi = S.psi[w];
@@ -1035,6 +1033,60 @@ __global__ __launch_bounds__(64 * WPB, 4) void k_sample(DevProblem P, WalkerArra
         S.wsum[2 * W + w] = st0;
         if (nbad) atomicAdd(S.bad, (unsigned long long)nbad);
     }
+}
+
+template <class R>
+__global__ __launch_bounds__(64 * WPB, 4) void k_sample(DevProblem P, WalkerArrays S, long long W, long long step0,
+                                                   int nsteps, long long burn_in, int NL) {
+    extern __shared__ unsigned char smem[];
+    int wave = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    long long w = (long long)blockIdx.x * WPB + wave;
+    if (w >= W) return;
+    WaveLDS L = carve(smem + wave * wave_lds_bytes(NL), NL);
+    sample_walker<R>(P, S, W, w, step0, nsteps, burn_in, L, lane);
+}
+
+// ---------------------------------------------------------------------------
+// Batched form: many independent systems (their own integrals, references,
+// class tables and walkers) in one launch.  A schedule maps each workgroup
+// slot to (system, walker); a walker's chain depends only on its own id and
+// the system's step counter, so any schedule gives the same results as the
+// systems walked one by one.
+// ---------------------------------------------------------------------------
+struct BatchSys {
+    DevProblem P;
+    WalkerArrays S;
+    long long W;         // walkers of the system
+    long long step0;     // global step index of its next step
+    long long burn_in;
+    int NL;              // list headers per group (LDS layout)
+    int pad;
+};
+
+template <class R>
+__global__ __launch_bounds__(64 * WPB, 4) void k_sample_batch(const BatchSys *sys, const int *slot_sys,
+                                                         const int *slot_w, long long nslots, int nsteps) {
+    extern __shared__ unsigned char smem[];
+    int wave = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    long long slot = (long long)blockIdx.x * WPB + wave;
+    if (slot >= nslots) return;
+    int s = uni(slot_sys[slot]);
+    long long w = (long long)uni(slot_w[slot]);
+    const BatchSys &B = sys[s];
+    DevProblem P = B.P;
+    WalkerArrays S = B.S;
+    int NL = uni(B.NL);
+    WaveLDS L = carve(smem + wave * wave_lds_bytes(NL), NL);
+    long long Wn = (long long)uni((unsigned long long)B.W), st0 = (long long)uni((unsigned long long)B.step0);
+    long long bi = (long long)uni((unsigned long long)B.burn_in);
+    sample_walker<R>(P, S, Wn, w, st0, nsteps, bi, L, lane);
+}
+
+// step counters of every system advance after a batched launch (kept on the
+// device so that a captured graph of launches can be replayed as is)
+__global__ void k_batch_advance(BatchSys *sys, int nsys, int nsteps) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < nsys) sys[s].step0 += nsteps;
 }
 
 // local energies without moving (parity / snapshots)

@@ -102,6 +102,12 @@ def lib():
             "scqmc_load_state": ([P, P, i64], C.c_int),
             "scqmc_optimize": ([P, C.POINTER(AMSGrad), i64, P, P], C.c_int),
             "scqmc_read_sc_coeffs": ([P, P, P, i64], C.c_int),
+            "scqmc_batch_create": ([P, i32, C.POINTER(P)], C.c_int),
+            "scqmc_batch_destroy": ([P], None),
+            "scqmc_batch_last_error": ([P], C.c_char_p),
+            "scqmc_batch_sample": ([P, i64], C.c_int),
+            "scqmc_batch_set_schedule": ([P, i32, i32], C.c_int),
+            "scqmc_batch_tune": ([P, i64, C.POINTER(i32), C.POINTER(i32), C.POINTER(dbl)], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -322,3 +328,43 @@ class Engine:
         self._check(lib().scqmc_load_state(self.h, buf, len(blob)))
         hdr = np.frombuffer(blob[:96], dtype=np.int64)
         self.n_walkers = int(hdr[2])
+
+
+class Batch:
+    """Several engines (systems) walked by one launch (see include/scqmc.h)."""
+
+    def __init__(self, engines):
+        self.engines = list(engines)   # keeps the contexts alive
+        arr = (C.c_void_p * len(self.engines))(*[e.h.value for e in self.engines])
+        h = C.c_void_p()
+        rc = lib().scqmc_batch_create(arr, len(self.engines), C.byref(h))
+        if rc != OK:
+            raise ScqmcError(rc, "scqmc_batch_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().scqmc_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != OK:
+            msg = lib().scqmc_batch_last_error(self.h)
+            raise ScqmcError(rc, msg.decode() if msg else "")
+
+    def sample(self, n_steps):
+        self._check(lib().scqmc_batch_sample(self.h, int(n_steps)))
+
+    def set_schedule(self, order, steps_per_launch):
+        self._check(lib().scqmc_batch_set_schedule(self.h, int(order), int(steps_per_launch)))
+
+    def tune(self, trial_steps):
+        o, sp, ms = C.c_int32(), C.c_int32(), C.c_double()
+        self._check(lib().scqmc_batch_tune(self.h, int(trial_steps), C.byref(o), C.byref(sp), C.byref(ms)))
+        return o.value, sp.value, ms.value

@@ -321,3 +321,34 @@ def make_tiny_problem(space: Space, seed: int, rank: int = 6, ref_fraction: floa
     c0, ccls = make_class_coeffs(space, coeff_seed if coeff_seed is not None else seed + 3)
     return Problem(name="tiny", space=space, h1=h1, chol=chol, e_const=0.25,
                    ref_dets=dets, ref_coeff=coeff, c0=c0, c_cls=ccls)
+
+
+def make_batch_systems(n_systems: int = 64, seed: int = 4001):
+    """Independent systems of uneven sizes for the batched form: CAS(A, A)
+    with A uniform over {4, 6, 8, 10, 12}; N uniform in [20, 80] orbitals with
+    n_core = max(1, round(0.1 N)) doubly occupied core orbitals (electrons =
+    2 n_core + A); Cholesky rank 2N; a synthetic selected-CI reference of
+    n_ref = min(log-uniform[100, 20000], half the CAS dimension) determinants
+    (half: the rejection sampler of make_sci_reference would otherwise spend
+    its time hunting the last rare determinants); walkers
+    256 + 7936 (n_ref - 100) / 19900, rounded to a multiple of 64.  Each system
+    gets its own seeds (integrals, reference, class coefficients, walkers)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(n_systems):
+        A = int(rng.choice([4, 6, 8, 10, 12]))
+        N = int(rng.integers(20, 81))
+        C = max(1, int(round(0.1 * N)))
+        sp = Space(N, C, A, C + A // 2, C + A // 2)
+        cas = math.comb(A, A // 2) ** 2
+        n_ref = int(min(round(math.exp(rng.uniform(math.log(100), math.log(20000)))), cas // 2))
+        W = 256 + (8192 - 256) * (n_ref - 100) / 19900.0
+        W = int(max(256, round(W / 64.0) * 64))
+        base = seed * 1000 + 10 * i
+        h1, chol = make_integrals(sp, 2 * N, base + 1)
+        dets, coeff = make_sci_reference(sp, n_ref, base + 2)
+        c0, ccls = make_class_coeffs(sp, base + 3)
+        out.append(Problem(name=f"batch{i}", space=sp, h1=h1, chol=chol, e_const=0.0,
+                           ref_dets=dets, ref_coeff=coeff, c0=c0, c_cls=ccls,
+                           n_walkers=W, n_steps=0, burn_in=0, seed_walk=base + 4))
+    return out
