@@ -200,6 +200,9 @@ scqmc_status scqmc_synchronize(scqmc_ctx *ctx);
 
 /* Host finalisation of the accumulated sums (synchronises). */
 scqmc_status scqmc_read_estimates(scqmc_ctx *ctx, scqmc_estimates *out);
+/* The E_var part of read_estimates alone (E_var, its jackknife error, a0^2),
+ * from the per-walker sums only -- cheap enough to poll (serving loops). */
+scqmc_status scqmc_read_energy(scqmc_ctx *ctx, double *e_var, double *e_var_err, double *a0_sq);
 /* Per-class sums (n == n_classes): t_l = sum t, te_l = sum t E_L,
  * n_l = sum t / c_l^2, d_l = sum t E_D,L / c_l^2 (synchronises). */
 scqmc_status scqmc_read_class_sums(scqmc_ctx *ctx, double *n_l, double *d_l, double *t_l, double *te_l, int64_t n);

@@ -887,13 +887,10 @@ static double e2_from_sums(const double *nl_, const double *dl_, long long n, do
     return e2;
 }
 
-scqmc_status scqmc_read_estimates(scqmc_ctx *c, scqmc_estimates *out) {
-    if (!c || !out) return SCQMC_E_INVALID_ARG;
-    if (!c->has_walkers) FAIL(c, SCQMC_E_STATE, "init_walkers first");
-    std::vector<double> ws, cs, gsum;
-    TRY(download_sums(c, ws, cs, &gsum));
+// E_var, a0^2 and their delete-one jackknife errors over min(W, 256) groups
+// of consecutive walkers, from the per-walker sums
+static void energy_from_walker_sums(const scqmc_ctx *c, const std::vector<double> &ws, scqmc_estimates *out) {
     long long W = c->W;
-    // delete-one jackknife over groups of consecutive walkers
     long long G = std::min<long long>(W, 256);
     std::vector<double> gt(G, 0.0), gte(G, 0.0), gt0(G, 0.0);
     for (long long w = 0; w < W; w++) {
@@ -928,6 +925,29 @@ scqmc_status scqmc_read_estimates(scqmc_ctx *c, scqmc_estimates *out) {
     } else {
         out->e_var = out->e_var_err = out->a0_sq = out->a0_sq_err = NAN;
     }
+}
+
+scqmc_status scqmc_read_energy(scqmc_ctx *c, double *e_var, double *e_var_err, double *a0_sq) {
+    if (!c) return SCQMC_E_INVALID_ARG;
+    if (!c->has_walkers) FAIL(c, SCQMC_E_STATE, "init_walkers first");
+    HIPCHK(c, hipSetDevice(c->device));
+    std::vector<double> ws(3 * c->W);
+    HIPCHK(c, hipMemcpyAsync(ws.data(), c->wsum.p, sizeof(double) * 3 * c->W, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    scqmc_estimates est;
+    energy_from_walker_sums(c, ws, &est);
+    if (e_var) *e_var = est.e_var;
+    if (e_var_err) *e_var_err = est.e_var_err;
+    if (a0_sq) *a0_sq = est.a0_sq;
+    return SCQMC_OK;
+}
+
+scqmc_status scqmc_read_estimates(scqmc_ctx *c, scqmc_estimates *out) {
+    if (!c || !out) return SCQMC_E_INVALID_ARG;
+    if (!c->has_walkers) FAIL(c, SCQMC_E_STATE, "init_walkers first");
+    std::vector<double> ws, cs, gsum;
+    TRY(download_sums(c, ws, cs, &gsum));
+    energy_from_walker_sums(c, ws, out);
     out->e_ref = c->has_dyall ? c->e0_ref : 0.0;
     out->davidson = c->has_dyall ? (1.0 - out->a0_sq) * (out->e_var - c->e0_ref) : NAN;
     out->e2 = NAN;

@@ -102,6 +102,7 @@ def lib():
             "scqmc_load_state": ([P, P, i64], C.c_int),
             "scqmc_optimize": ([P, C.POINTER(AMSGrad), i64, P, P], C.c_int),
             "scqmc_read_sc_coeffs": ([P, P, P, i64], C.c_int),
+            "scqmc_read_energy": ([P, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(dbl)], C.c_int),
             "scqmc_batch_create": ([P, i32, C.POINTER(P)], C.c_int),
             "scqmc_batch_destroy": ([P], None),
             "scqmc_batch_last_error": ([P], C.c_char_p),
@@ -255,6 +256,11 @@ class Engine:
         e = Estimates()
         self._check(lib().scqmc_read_estimates(self.h, C.byref(e)))
         return e.as_dict()
+
+    def read_energy(self):
+        e, s, a = C.c_double(), C.c_double(), C.c_double()
+        self._check(lib().scqmc_read_energy(self.h, C.byref(e), C.byref(s), C.byref(a)))
+        return e.value, s.value, a.value
 
     def read_class_sums(self):
         n = self.n_classes

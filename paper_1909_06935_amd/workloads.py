@@ -352,3 +352,45 @@ def make_batch_systems(n_systems: int = 64, seed: int = 4001):
                            ref_dets=dets, ref_coeff=coeff, c0=c0, c_cls=ccls,
                            n_walkers=W, n_steps=0, burn_in=0, seed_walk=base + 4))
     return out
+
+
+def make_scan_requests(n_requests: int = 100, rate: float = 4.0, n_templates: int = 8, seed: int = 5001):
+    """Potential-energy-scan requests for the serving loop: Poisson arrivals
+    (exponential gaps of mean 1/rate seconds); each request is one of
+    n_templates systems of the batched-form recipe (at most 40 orbitals and
+    2,000 reference determinants, so that a request solves in seconds) at a
+    geometry parameter lam ~ U[0, 1]: h1(lam) = h1 + lam D1 and
+    B(lam) = B + lam D2 with fixed random symmetric D1, D2 (N(0, 0.02))
+    per template.  Returns (templates, requests); a request is a dict with
+    id, arrival time, template index, lam and its own walker seed."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pool = [p for p in make_batch_systems(48, seed=seed + 1)
+            if p.space.n_orb <= 40 and len(p.ref_coeff) <= 2000][:n_templates]
+    templates = []
+    for k, p in enumerate(pool):
+        n = p.space.n_orb
+        r2 = np.random.Generator(np.random.PCG64(seed * 100 + k))
+        d1 = np.triu(r2.normal(0.0, 0.02, size=(n, n)))
+        d1 = d1 + np.triu(d1, 1).T
+        d2 = np.zeros_like(p.chol)
+        iu = np.triu_indices(n)
+        for L in range(p.chol.shape[0]):
+            b = np.zeros((n, n))
+            b[iu] = r2.normal(0.0, 0.02, size=len(iu[0]))
+            d2[L] = b + np.triu(b, 1).T
+        templates.append((p, d1, d2))
+    t = 0.0
+    reqs = []
+    for i in range(n_requests):
+        t += float(rng.exponential(1.0 / rate))
+        reqs.append(dict(id=i, arrival=t, template=int(rng.integers(len(templates))), lam=float(rng.random()),
+                         seed=seed * 10000 + i))
+    return templates, reqs
+
+
+def scan_problem(template, lam: float, seed_walk: int) -> Problem:
+    """The system of one scan request (integrals at geometry parameter lam)."""
+    p, d1, d2 = template
+    return Problem(name=p.name, space=p.space, h1=p.h1 + lam * d1, chol=p.chol + lam * d2, e_const=0.0,
+                   ref_dets=p.ref_dets, ref_coeff=p.ref_coeff, c0=p.c0, c_cls=p.c_cls,
+                   n_walkers=p.n_walkers, n_steps=0, burn_in=0, seed_walk=seed_walk)

@@ -1,0 +1,30 @@
+"""Serving loop: requests admitted as memory frees up and walked together
+give exactly the result each gives walked alone for the same steps."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1909_06935_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("budget_systems", [100, 2])
+def test_serve_mix_equals_alone(budget_systems):
+    from paper_1909_06935_amd.serve import Server, footprint_bytes
+    templates, reqs = wl.make_scan_requests(n_requests=6, rate=1000.0, n_templates=3)
+    fps = [footprint_bytes(wl.scan_problem(templates[r["template"]], r["lam"], r["seed"])) for r in reqs]
+    budget = int(sorted(fps)[-1] * budget_systems)
+    srv = Server(templates, hbm_budget=budget, target_err=0.0, chunk=8, burn_in=4, min_steps=8, max_steps=32)
+    res = srv.run(reqs, realtime=False)
+    _say("served", [(r.id, r.steps, round(r.e_var, 6)) for r in res])
+    for req, r in zip(reqs, res):
+        assert r.steps == 32
+        e, err, _ = srv.solve_alone(req, r.steps)
+        assert e == r.e_var and err == r.e_err, (req["id"], e, r.e_var)
