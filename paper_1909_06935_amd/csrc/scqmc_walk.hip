@@ -376,7 +376,9 @@ __device__ __forceinline__ double fock_y(const DevProblem &P, const WalkerCtx &W
 // the top byte of .y (ascending r; empty ones may be left out).
 template <bool U, class R, class ListFn, class FockFn>
 __device__ double phi1(const DevProblem &P, unsigned long long y, int s, int nl, ListFn lists, FockFn fock) {
-    int sg = s >= P.V;
+    // every row that calls this in one sweep has its virtual electron in the
+    // same spin (fixed by the block), so the spin is wave-uniform
+    int sg = uni((int)(s >= P.V));
     int gs = g_of_virtual(P, s);
     int bs = sg ? P.nea + P.neb : P.nea;   // electrons below s in any active-space determinant
     double acc1 = 0.0;
@@ -394,15 +396,20 @@ __device__ double phi1(const DevProblem &P, unsigned long long y, int s, int nl,
     unsigned Np = (unsigned)P.Np, N2 = Np * Np, N3 = N2 * Np;
     unsigned sp = (unsigned)g_idx(P, gs);
     const R *E = Ints<R>::eri(P);
+    // The sign: with Q1 < Q2 the added pair {s, r}, b(Q) the electrons of the
+    // reference determinant below Q, (-1)^e with
+    // e = b(Q1) + b(Q2) - sum_{Q in {Q1,Q2}} [(P1 < Q) + (P2 < Q)]
+    //   = bs + br - [(P1 < s) + (P2 < s) + (P1 < r) + (P2 < r)]
+    // (symmetric in Q1, Q2).  An active P precedes the virtual s when P is
+    // alpha or s is beta; s precedes r exactly when s is alpha and r beta.
     for (int li = 1; li <= nl; li++) {
         uint2 ox = lists(li);
         unsigned cnt = ox.y & 0xFFFFFFu;
         if (!cnt) continue;
         int r = (int)(ox.y >> 24);
         int gr = g_of_active(P, r);
-        int Q1 = gs < gr ? gs : gr, Q2 = gs < gr ? gr : gs;
-        bool s_first = gs < gr;
         int sr = r >> 5;                         // spin of r
+        bool s_first = (sg == 0) && (sr == 1);
         unsigned rr = (unsigned)(r & 31);
         unsigned long long yr = y & ~(1ull << r);
         for (unsigned k = 0; k < cnt; k++) {
@@ -411,10 +418,9 @@ __device__ double phi1(const DevProblem &P, unsigned long long y, int s, int nl,
             if (t == r || u == r) continue;
             double w = tload<U>(P.xtab.vals, ox.x + k);
             int P1 = g_of_active(P, t), P2 = g_of_active(P, u);
-            int br = key_below(yr | (1ull << t) | (1ull << u), r);
-            int b1 = Q1 == gs ? bs : br, b2 = Q2 == gs ? bs : br;
-            int e = b2 - (P1 < Q2) - (P2 < Q2) + b1 - (P1 < Q1) - (P2 < Q1);
             int st = t >> 5, su = u >> 5;
+            int br = key_below(yr | (1ull << t) | (1ull << u), r);
+            int e = bs + br - ((st == 0 || sg == 1) + (su == 0 || sg == 1) + (P1 < gr) + (P2 < gr));
             unsigned p1 = (unsigned)(t & 31), p2 = (unsigned)(u & 31);
             R J = (st == sg && su == sr) ? E[p2 * N3 + rr * N2 + p1 * Np + sp] : R(0);
             R K = (su == sg && st == sr) ? E[p1 * N3 + rr * N2 + p2 * Np + sp] : R(0);
