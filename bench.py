@@ -154,8 +154,9 @@ def main():
         print(json.dumps({"calib_copy_mib": args.calib_copy, "launches": 5}))
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is described, "
-              "not launched, in this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): walkers are independent, so a "
+              "multi-GPU job is N copies of this run with disjoint walker ids; it is not launched here",
+              file=sys.stderr)
         sys.exit(2)
 
     if args.config == "batch":

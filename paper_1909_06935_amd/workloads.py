@@ -141,7 +141,7 @@ def sort_dets(dets: np.ndarray, coeff: Optional[np.ndarray] = None):
 
 
 # ---------------------------------------------------------------------------
-# integrals (BASELINE generator: graded h1 diagonal, low-rank Gaussian ERI)
+# integrals (graded h1 diagonal, low-rank Gaussian ERI)
 # ---------------------------------------------------------------------------
 
 def make_integrals(space: Space, rank: int, seed: int, sigma: float = 0.1):

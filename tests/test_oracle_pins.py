@@ -185,8 +185,9 @@ def test_closed_form_counts_cfg2_cas_walker():
     assert len(nb["h"]) == brute.count_neighbors(8, 28, [4, 4], [0, 0]) == 22592
 
 
-def test_survey_counts_closed_form():
-    # App. A style counts: CAS / S-1 / S-2(aa) / S-2(ab) walkers
+def test_neighbour_counts_closed_form():
+    # neighbour counts of a CAS walker, one virtual electron, two same-spin and
+    # two opposite-spin virtual electrons (4 active / 6 virtual, 14 / 76)
     kinds = [([2, 2], [0, 0]), ([1, 2], [1, 0]), ([0, 2], [2, 0]), ([1, 1], [1, 1])]
     assert [brute.count_neighbors(4, 6, *o) for o in kinds] == [344, 269, 209, 209]
     kinds = [([7, 7], [0, 0]), ([6, 7], [1, 0]), ([5, 7], [2, 0]), ([6, 6], [1, 1])]
