@@ -77,6 +77,7 @@ struct scqmc_ctx {
     std::vector<double> am_m, am_v, am_vmax;   // AMSGrad moments (classes 1..n_classes-1)
     unsigned long long seed = 0;
     DBuf wkey, wvirt, wpsi, wsum, cacc, bad;
+    DBuf worder;   // walker of each workgroup slot of a k_sample launch
     // snapshot scratch
     DBuf skey, svirt, svalid;
 };
@@ -769,6 +770,7 @@ scqmc_status scqmc_init_walkers(scqmc_ctx *c, int64_t W, const uint64_t *dets, u
     HIPCHK(c, hipSetDevice(c->device));
     TRY(dalloc(c, c->wkey, sizeof(unsigned long long) * W));
     TRY(dalloc(c, c->wvirt, sizeof(unsigned) * W));
+    TRY(dalloc(c, c->worder, sizeof(int) * W));
     TRY(dalloc(c, c->wpsi, sizeof(double) * W));
     TRY(dalloc(c, c->wsum, sizeof(double) * 3 * W));
     c->ncg = class_groups(W);
@@ -802,14 +804,9 @@ scqmc_status scqmc_init_walkers(scqmc_ctx *c, int64_t W, const uint64_t *dets, u
     return SCQMC_OK;
 }
 
-scqmc_status scqmc_sample(scqmc_ctx *c, int64_t n_steps) {
-    if (!c) return SCQMC_E_INVALID_ARG;
-    if (!c->has_walkers) FAIL(c, SCQMC_E_STATE, "init_walkers first");
-    if (c->opt.mode == 1 && !c->has_dyall) FAIL(c, SCQMC_E_STATE, "mode 1 needs set_dyall");
-    if (n_steps < 0) FAIL(c, SCQMC_E_INVALID_ARG, "negative n_steps");
-    if (c->step + n_steps >= (1LL << 31)) FAIL(c, SCQMC_E_UNSUPPORTED, "step counter limit (2^31) reached");
-    HIPCHK(c, hipSetDevice(c->device));
-    TRY(ensure_f32(c));
+// n_steps steps of every walker in launches of block_len steps, each launch
+// preceded by the walker order of its dispatch (k_order)
+static scqmc_status launch_sample(scqmc_ctx *c, long long n_steps, long long burn_in) {
     DevProblem P = dev_problem(c);
     WalkerArrays S;
     S.key = c->wkey.as<unsigned long long>();
@@ -821,19 +818,32 @@ scqmc_status scqmc_sample(scqmc_ctx *c, int64_t n_steps) {
     S.bad = c->bad.as<unsigned long long>();
     int NL = lists_per_group(c);
     size_t lds = kernel_lds(c);
+    int *order = c->worder.as<int>();
     long long blk = c->opt.block_len > 0 ? c->opt.block_len : 1;
     for (long long done = 0; done < n_steps; done += blk) {
         int ns = (int)std::min(blk, n_steps - done);
+        hipLaunchKernelGGL(k_order, dim3(1), dim3(1024), 0, c->stream, c->wvirt.as<const unsigned>(), c->W, order);
         if (c->opt.precision == 1)
-            hipLaunchKernelGGL(k_sample<float>, dim3(grid1(c->W, WPB)), dim3(64 * WPB), lds, c->stream, P, S, c->W,
-                               c->step + done, ns, (long long)c->opt.burn_in, NL);
+            hipLaunchKernelGGL(k_sample<float>, dim3(grid1(c->W, WPB)), dim3(64 * WPB), lds, c->stream, P, S, order,
+                               c->W, c->step + done, ns, burn_in, NL);
         else
-            hipLaunchKernelGGL(k_sample<double>, dim3(grid1(c->W, WPB)), dim3(64 * WPB), lds, c->stream, P, S, c->W,
-                               c->step + done, ns, (long long)c->opt.burn_in, NL);
+            hipLaunchKernelGGL(k_sample<double>, dim3(grid1(c->W, WPB)), dim3(64 * WPB), lds, c->stream, P, S, order,
+                               c->W, c->step + done, ns, burn_in, NL);
         HIPCHK(c, hipGetLastError());
     }
     c->step += n_steps;
     return SCQMC_OK;
+}
+
+scqmc_status scqmc_sample(scqmc_ctx *c, int64_t n_steps) {
+    if (!c) return SCQMC_E_INVALID_ARG;
+    if (!c->has_walkers) FAIL(c, SCQMC_E_STATE, "init_walkers first");
+    if (c->opt.mode == 1 && !c->has_dyall) FAIL(c, SCQMC_E_STATE, "mode 1 needs set_dyall");
+    if (n_steps < 0) FAIL(c, SCQMC_E_INVALID_ARG, "negative n_steps");
+    if (c->step + n_steps >= (1LL << 31)) FAIL(c, SCQMC_E_UNSUPPORTED, "step counter limit (2^31) reached");
+    HIPCHK(c, hipSetDevice(c->device));
+    TRY(ensure_f32(c));
+    return launch_sample(c, n_steps, (long long)c->opt.burn_in);
 }
 
 scqmc_status scqmc_synchronize(scqmc_ctx *c) {
@@ -1171,6 +1181,7 @@ scqmc_status scqmc_load_state(scqmc_ctx *c, const void *buf, int64_t len) {
     HIPCHK(c, hipSetDevice(c->device));
     TRY(dalloc(c, c->wkey, 8 * W));
     TRY(dalloc(c, c->wvirt, 4 * W));
+    TRY(dalloc(c, c->worder, 4 * W));
     TRY(dalloc(c, c->wpsi, 8 * W));
     TRY(dalloc(c, c->wsum, 24 * W));
     TRY(dalloc(c, c->cacc, class_acc_bytes(c)));
@@ -1192,32 +1203,7 @@ scqmc_status scqmc_load_state(scqmc_ctx *c, const void *buf, int64_t len) {
 // ---------------------------------------------------------------------------
 // SC coefficient optimisation ("SC-MRCI(s)"): AMSGrad on the sampled gradient
 // ---------------------------------------------------------------------------
-static scqmc_status launch_sample(scqmc_ctx *c, long long n_steps, long long burn_in) {
-    DevProblem P = dev_problem(c);
-    WalkerArrays S;
-    S.key = c->wkey.as<unsigned long long>();
-    S.virt = c->wvirt.as<unsigned>();
-    S.psi = c->wpsi.as<double>();
-    S.wsum = c->wsum.as<double>();
-    S.cacc = c->cacc.as<unsigned long long>();
-    S.ncg = (int)c->ncg;
-    S.bad = c->bad.as<unsigned long long>();
-    int NL = lists_per_group(c);
-    size_t lds = kernel_lds(c);
-    long long blk = c->opt.block_len > 0 ? c->opt.block_len : 1;
-    for (long long done = 0; done < n_steps; done += blk) {
-        int ns = (int)std::min(blk, n_steps - done);
-        if (c->opt.precision == 1)
-            hipLaunchKernelGGL(k_sample<float>, dim3(grid1(c->W, WPB)), dim3(64 * WPB), lds, c->stream, P, S, c->W,
-                               c->step + done, ns, burn_in, NL);
-        else
-            hipLaunchKernelGGL(k_sample<double>, dim3(grid1(c->W, WPB)), dim3(64 * WPB), lds, c->stream, P, S, c->W,
-                               c->step + done, ns, burn_in, NL);
-        HIPCHK(c, hipGetLastError());
-    }
-    c->step += n_steps;
-    return SCQMC_OK;
-}
+
 
 static scqmc_status refresh_psi(scqmc_ctx *c) {
     DevProblem P = dev_problem(c);

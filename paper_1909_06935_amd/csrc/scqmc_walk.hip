@@ -1041,13 +1041,52 @@ __device__ __forceinline__ void sample_walker(const DevProblem &P, const WalkerA
     }
 }
 
+// Launch order of the walkers: a walker's cost grows with its neighbour count,
+// which is largest with no virtual electron and smallest with two, so walkers
+// are dispatched by ascending virtual-electron count (stable within a count).
+// The costly walks then start first and the launch does not end waiting on a
+// few late ones.  Only the schedule changes: a walker's chain depends on its
+// own id.  One workgroup of 1024 threads: counting sort over three keys.
+__global__ __launch_bounds__(1024) void k_order(const unsigned *virt, long long W, int *order) {
+    __shared__ int sc[3][1024];
+    int t = threadIdx.x;
+    long long per = (W + 1023) / 1024;
+    long long lo = min(W, (long long)t * per), hi = min(W, lo + per);
+    int c[3] = {0, 0, 0};
+    for (long long i = lo; i < hi; i++) {
+        unsigned v = virt[i];
+        c[((v & 0xFFFFu) != SCQ_NOVIRT) + ((v >> 16) != SCQ_NOVIRT)]++;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; k++) sc[k][t] = c[k];
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        int v[3];
+#pragma unroll
+        for (int k = 0; k < 3; k++) v[k] = t >= d ? sc[k][t - d] : 0;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 3; k++) sc[k][t] += v[k];
+        __syncthreads();
+    }
+    int n0 = sc[0][1023], n1 = sc[1][1023];
+    int base[3] = {sc[0][t] - c[0], n0 + sc[1][t] - c[1], n0 + n1 + sc[2][t] - c[2]};
+    for (long long i = lo; i < hi; i++) {
+        unsigned v = virt[i];
+        int k = ((v & 0xFFFFu) != SCQ_NOVIRT) + ((v >> 16) != SCQ_NOVIRT);
+        order[base[k]++] = (int)i;
+    }
+}
+
+// order: walker of each workgroup slot (a permutation of 0..W-1)
 template <class R>
-__global__ __launch_bounds__(64 * WPB, 4) void k_sample(DevProblem P, WalkerArrays S, long long W, long long step0,
-                                                   int nsteps, long long burn_in, int NL) {
+__global__ __launch_bounds__(64 * WPB, 4) void k_sample(DevProblem P, WalkerArrays S, const int *order, long long W,
+                                                   long long step0, int nsteps, long long burn_in, int NL) {
     extern __shared__ unsigned char smem[];
     int wave = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
-    long long w = (long long)blockIdx.x * WPB + wave;
-    if (w >= W) return;
+    long long slot = (long long)blockIdx.x * WPB + wave;
+    if (slot >= W) return;
+    long long w = (long long)uni(order[slot]);
     WaveLDS L = carve(smem + wave * wave_lds_bytes(NL), NL);
     sample_walker<R>(P, S, W, w, step0, nsteps, burn_in, L, lane);
 }
