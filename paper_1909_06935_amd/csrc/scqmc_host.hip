@@ -1400,6 +1400,7 @@ scqmc_status batch_upload(scqmc_batch *b) {
         B.S.cacc = c->cacc.as<unsigned long long>();
         B.S.ncg = (int)c->ncg;
         B.S.bad = c->bad.as<unsigned long long>();
+        B.order = c->worder.as<int>();
         B.W = c->W;
         B.step0 = c->step;
         B.burn_in = c->opt.burn_in;
@@ -1422,6 +1423,7 @@ scqmc_status batch_upload(scqmc_batch *b) {
 scqmc_status batch_launch(scqmc_batch *b, int nsteps) {
     int n = (int)b->ctx.size();
     dim3 grid(grid1(b->nslots, WPB)), blk(64 * WPB);
+    hipLaunchKernelGGL(k_order_batch, dim3(n), dim3(1024), 0, b->stream, b->dsys.as<const BatchSys>());
     if (b->precision == 1)
         hipLaunchKernelGGL(k_sample_batch<float>, grid, blk, b->lds, b->stream, b->dsys.as<const BatchSys>(),
                            b->dslot_sys.as<const int>(), b->dslot_w.as<const int>(), b->nslots, nsteps);

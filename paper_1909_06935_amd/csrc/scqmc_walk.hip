@@ -368,17 +368,16 @@ __device__ __forceinline__ double fock_y(const DevProblem &P, const WalkerCtx &W
     return v;
 }
 
-// <m|H|phi0> for m = y + virtual s.  Table coefficients carry the part of each
-// Slater-Condon phase that depends on the reference determinant (the
-// annihilation of its removed electrons); the rest depends on spins and on the
-// electron r only.  `fock` gives the single-excitation element.
+// <m|H|phi0> for m = y + virtual s of spin sg (0 alpha, 1 beta).  Table
+// coefficients carry the part of each Slater-Condon phase that depends on the
+// reference determinant (the annihilation of its removed electrons); the rest
+// depends on spins and on the electron r only.  `fock` gives the
+// single-excitation element.
 // lists(0) is the y-list of y; lists(1..nl) are x-lists of y - r with r in
 // the top byte of .y (ascending r; empty ones may be left out).
 template <bool U, class R, class ListFn, class FockFn>
-__device__ double phi1(const DevProblem &P, unsigned long long y, int s, int nl, ListFn lists, FockFn fock) {
-    // every row that calls this in one sweep has its virtual electron in the
-    // same spin (fixed by the block), so the spin is wave-uniform
-    int sg = uni((int)(s >= P.V));
+__device__ double phi1(const DevProblem &P, unsigned long long y, int s, int sg, int nl, ListFn lists,
+                       FockFn fock) {
     int gs = g_of_virtual(P, s);
     int bs = sg ? P.nea + P.neb : P.nea;   // electrons below s in any active-space determinant
     double acc1 = 0.0;
@@ -469,7 +468,7 @@ __device__ double psi_direct(const DevProblem &P, unsigned long long key, unsign
     }
     if (nv == 1) {
         double phi = phi1<false, R>(
-            P, key, vcode[0], popc64(key),
+            P, key, vcode[0], (int)(vcode[0] >= P.V), popc64(key),
             [&](int k) -> uint2 {
                 if (k == 0) return table_find(P.ytab, key);
                 unsigned long long y = key;
@@ -636,7 +635,10 @@ __device__ __forceinline__ void row_eval(const DevProblem &P, const WalkerCtx &W
     if (VP == 0) {
         phi = G.phi;
     } else if (VP == 1) {
-        phi = phi1<U, R>(P, G.xkey, d.Lp0, G.nl, [&](int k) -> uint2 { return view_list<U>(G, k); },
+        // the block fixes the spin of the one virtual electron, so it is the
+        // same for every row of the wave: a scalar
+        phi = phi1<U, R>(P, G.xkey, d.Lp0, uni((int)(d.Lp0 >= P.V)), G.nl,
+                         [&](int k) -> uint2 { return view_list<U>(G, k); },
                          [&](int gT, int gS) -> double { return fock_y<R>(P, W, L, G.rg0, G.rg1, G.pg0, G.pg1, gT, gS); });
     } else {
         phi = phi2<U, R>(P, d.Lp0, d.Lp1, view_list<U>(G, 0));
@@ -1047,16 +1049,16 @@ __device__ __forceinline__ void sample_walker(const DevProblem &P, const WalkerA
 // The costly walks then start first and the launch does not end waiting on a
 // few late ones.  Only the schedule changes: a walker's chain depends on its
 // own id.  One workgroup of 1024 threads: counting sort over three keys.
-__global__ __launch_bounds__(1024) void k_order(const unsigned *virt, long long W, int *order) {
+__device__ __forceinline__ int virt_count(unsigned v) {
+    return ((v & 0xFFFFu) != SCQ_NOVIRT) + ((v >> 16) != SCQ_NOVIRT);
+}
+__device__ void order_walkers(const unsigned *virt, long long W, int *order) {
     __shared__ int sc[3][1024];
     int t = threadIdx.x;
     long long per = (W + 1023) / 1024;
     long long lo = min(W, (long long)t * per), hi = min(W, lo + per);
     int c[3] = {0, 0, 0};
-    for (long long i = lo; i < hi; i++) {
-        unsigned v = virt[i];
-        c[((v & 0xFFFFu) != SCQ_NOVIRT) + ((v >> 16) != SCQ_NOVIRT)]++;
-    }
+    for (long long i = lo; i < hi; i++) c[virt_count(virt[i])]++;
 #pragma unroll
     for (int k = 0; k < 3; k++) sc[k][t] = c[k];
     __syncthreads();
@@ -1071,11 +1073,10 @@ __global__ __launch_bounds__(1024) void k_order(const unsigned *virt, long long 
     }
     int n0 = sc[0][1023], n1 = sc[1][1023];
     int base[3] = {sc[0][t] - c[0], n0 + sc[1][t] - c[1], n0 + n1 + sc[2][t] - c[2]};
-    for (long long i = lo; i < hi; i++) {
-        unsigned v = virt[i];
-        int k = ((v & 0xFFFFu) != SCQ_NOVIRT) + ((v >> 16) != SCQ_NOVIRT);
-        order[base[k]++] = (int)i;
-    }
+    for (long long i = lo; i < hi; i++) order[base[virt_count(virt[i])]++] = (int)i;
+}
+__global__ __launch_bounds__(1024) void k_order(const unsigned *virt, long long W, int *order) {
+    order_walkers(virt, W, order);
 }
 
 // order: walker of each workgroup slot (a permutation of 0..W-1)
@@ -1101,6 +1102,7 @@ __global__ __launch_bounds__(64 * WPB, 4) void k_sample(DevProblem P, WalkerArra
 struct BatchSys {
     DevProblem P;
     WalkerArrays S;
+    int *order;          // walker of each rank (k_order_batch)
     long long W;         // walkers of the system
     long long step0;     // global step index of its next step
     long long burn_in;
@@ -1108,6 +1110,13 @@ struct BatchSys {
     int pad;
 };
 
+// every system's walker order (one workgroup per system)
+__global__ __launch_bounds__(1024) void k_order_batch(const BatchSys *sys) {
+    const BatchSys &B = sys[blockIdx.x];
+    order_walkers(B.S.virt, B.W, B.order);
+}
+
+// slot -> (system, rank): the rank's walker comes from the system's order
 template <class R>
 __global__ __launch_bounds__(64 * WPB, 4) void k_sample_batch(const BatchSys *sys, const int *slot_sys,
                                                          const int *slot_w, long long nslots, int nsteps) {
@@ -1116,8 +1125,8 @@ __global__ __launch_bounds__(64 * WPB, 4) void k_sample_batch(const BatchSys *sy
     long long slot = (long long)blockIdx.x * WPB + wave;
     if (slot >= nslots) return;
     int s = uni(slot_sys[slot]);
-    long long w = (long long)uni(slot_w[slot]);
     const BatchSys &B = sys[s];
+    long long w = (long long)uni(B.order[slot_w[slot]]);
     DevProblem P = B.P;
     WalkerArrays S = B.S;
     int NL = uni(B.NL);

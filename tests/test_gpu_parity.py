@@ -169,3 +169,46 @@ def test_cfg3_counts_and_foi_snapshot():
         a_occ = [sum(sp.n_core <= p < sp.n_core + sp.n_act for p in oa), sum(sp.n_core <= p < sp.n_core + sp.n_act for p in ob)]
         nn[i] = brute.count_neighbors(14, 76, a_occ, list(virtual_count(sp, d)))
     compare_eval(eng.eval_snapshot(pick), ref, nn, "cfg3")
+
+
+@pytest.mark.parametrize("which", ["tiny0", "tiny3", "cfg1", "cfg2"])
+def test_walker_psi_every_class(which):
+    """psi of walkers set up by init_walkers (one determinant per thread) for
+    every kind -- active space, one virtual electron of either spin, two of
+    like or unlike spins -- mixed inside one wave, against the oracle; then
+    again after one coefficient update (the walkers' psi are recomputed with
+    the new coefficients)."""
+    if which.startswith("tiny"):
+        prob = tiny_problem(TINY[int(which[-1])])
+    elif which == "cfg1":
+        prob = cfg1_problem()
+    else:
+        prob = wl.make_problem("cfg2")
+        prob.eps_virt = np.linspace(1.0, 3.0, prob.space.n_virt)
+        prob.e0_ref = float(np.load(wl.reference_file("cfg2"))["e_cas"])
+    _say(f"walker psi {which}")
+    orc = O.Oracle.from_problem(prob, mode=0)
+    dets = sample_by_class(orc, prob.space, prob.ref_dets, 12, 99)
+    rng = np.random.Generator(np.random.PCG64(3))
+    dets = dets[rng.permutation(len(dets))]
+    kinds = {tuple(int(x) for x in _vc(prob.space, d)) for d in dets}
+    assert len(kinds) >= 3, kinds
+    eng = engine_for(prob, mode=0)
+    eng.init_walkers(dets, 5)
+    _, psi = eng.read_walkers()
+    ref = orc.eval(dets)["psi"]
+    scale = np.abs(ref).max()
+    assert np.all(np.abs(psi - ref) <= 1e-12 * scale), np.abs(psi - ref).max() / scale
+    eng.optimize(1, lr=0.02, steps_per_iter=2, equil_steps=0)
+    d2, psi2 = eng.read_walkers()
+    c0, c = eng.read_sc_coeffs()
+    p2 = wl.Problem(**{**prob.__dict__})
+    p2.c_cls = c
+    ref2 = O.Oracle.from_problem(p2, mode=0).eval(d2)["psi"]
+    scale = np.abs(ref2).max()
+    assert np.all(np.abs(psi2 - ref2) <= 1e-12 * scale), np.abs(psi2 - ref2).max() / scale
+
+
+def _vc(space, d):
+    from helpers import virtual_count
+    return virtual_count(space, d)
