@@ -1045,20 +1045,32 @@ __device__ __forceinline__ void sample_walker(const DevProblem &P, const WalkerA
 
 // Launch order of the walkers: a walker's cost grows with its neighbour count,
 // which is largest with no virtual electron and smallest with two, so walkers
-// are dispatched by ascending virtual-electron count (stable within a count).
-// The costly walks then start first and the launch does not end waiting on a
-// few late ones.  Only the schedule changes: a walker's chain depends on its
-// own id.  One workgroup of 1024 threads: counting sort over three keys.
+// are dispatched by ascending virtual-electron count.  The costly walks then
+// start first and the launch does not end waiting on a few late ones.  Only
+// the schedule changes: a walker's chain depends on its own id.  One
+// workgroup of 1024 threads, counting sort over the three counts: thread t
+// takes walkers t, t + 1024, t + 2048, ... (coalesced, OB loads in flight), a
+// scan of the per-thread counts gives each thread its output positions, so
+// the order inside a count is fixed (by thread, then by walker).
 __device__ __forceinline__ int virt_count(unsigned v) {
     return ((v & 0xFFFFu) != SCQ_NOVIRT) + ((v >> 16) != SCQ_NOVIRT);
 }
+#define OB 16
 __device__ void order_walkers(const unsigned *virt, long long W, int *order) {
     __shared__ int sc[3][1024];
     int t = threadIdx.x;
-    long long per = (W + 1023) / 1024;
-    long long lo = min(W, (long long)t * per), hi = min(W, lo + per);
     int c[3] = {0, 0, 0};
-    for (long long i = lo; i < hi; i++) c[virt_count(virt[i])]++;
+    for (long long i0 = t; i0 < W; i0 += 1024LL * OB) {
+        unsigned v[OB];
+#pragma unroll
+        for (int k = 0; k < OB; k++) {
+            long long i = i0 + 1024LL * k;
+            v[k] = i < W ? virt[i] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < OB; k++)
+            if (i0 + 1024LL * k < W) c[virt_count(v[k])]++;
+    }
 #pragma unroll
     for (int k = 0; k < 3; k++) sc[k][t] = c[k];
     __syncthreads();
@@ -1073,7 +1085,19 @@ __device__ void order_walkers(const unsigned *virt, long long W, int *order) {
     }
     int n0 = sc[0][1023], n1 = sc[1][1023];
     int base[3] = {sc[0][t] - c[0], n0 + sc[1][t] - c[1], n0 + n1 + sc[2][t] - c[2]};
-    for (long long i = lo; i < hi; i++) order[base[virt_count(virt[i])]++] = (int)i;
+    for (long long i0 = t; i0 < W; i0 += 1024LL * OB) {
+        unsigned v[OB];
+#pragma unroll
+        for (int k = 0; k < OB; k++) {
+            long long i = i0 + 1024LL * k;
+            v[k] = i < W ? virt[i] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < OB; k++) {
+            long long i = i0 + 1024LL * k;
+            if (i < W) order[base[virt_count(v[k])]++] = (int)i;
+        }
+    }
 }
 __global__ __launch_bounds__(1024) void k_order(const unsigned *virt, long long W, int *order) {
     order_walkers(virt, W, order);

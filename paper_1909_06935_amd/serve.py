@@ -26,6 +26,32 @@ from . import workloads as wl
 from .scqmc import Batch, Engine
 
 
+def prepare_templates(templates, n_iter: int = 100, lr: float = 0.02, steps_per_iter: int = 10,
+                      equil_steps: int = 5, seed: int = 7):
+    """SC coefficients of each scan template optimised once, at its reference
+    geometry (lam = 0), with the library's AMSGrad (scqmc_optimize); the
+    requests of a scan then reuse them, as the coefficients of nearby
+    geometries differ little.  Returns (templates with the optimised
+    coefficients, seconds spent per template)."""
+    out, secs = [], []
+    for tpl in templates:
+        p, d1, d2 = tpl
+        t0 = time.perf_counter()
+        prob = wl.scan_problem(tpl, 0.0, seed)
+        eng = Engine.from_problem(prob, mode=0, burn_in=0, block_len=0)
+        eng.init_walkers(wl.draw_walkers(prob.ref_dets, prob.ref_coeff, prob.n_walkers, prob.seed_walk),
+                         prob.seed_walk)
+        eng.sample(50)
+        eng.optimize(n_iter, lr=lr, steps_per_iter=steps_per_iter, equil_steps=equil_steps)
+        _, c = eng.read_sc_coeffs()
+        eng.close()
+        q = wl.Problem(**{**p.__dict__})
+        q.c_cls = c
+        out.append((q, d1, d2))
+        secs.append(time.perf_counter() - t0)
+    return out, secs
+
+
 def footprint_bytes(prob) -> int:
     """Device memory one request holds (integrals: the full N^4 block during
     set-up and the non-core block kept; reference tables; walkers)."""

@@ -28,3 +28,20 @@ def test_serve_mix_equals_alone(budget_systems):
         assert r.steps == 32
         e, err, _ = srv.solve_alone(req, r.steps)
         assert e == r.e_var and err == r.e_err, (req["id"], e, r.e_var)
+
+
+def test_serve_with_optimised_templates():
+    """Templates whose SC coefficients were optimised once (prepare_templates)
+    serve requests that again equal the request walked alone."""
+    from paper_1909_06935_amd.serve import Server, prepare_templates
+    templates, reqs = wl.make_scan_requests(n_requests=3, rate=1000.0, n_templates=2)
+    opt, secs = prepare_templates(templates, n_iter=3, steps_per_iter=4, equil_steps=2)
+    assert len(opt) == len(templates) and all(t > 0 for t in secs)
+    for (p, _, _), (q, _, _) in zip(templates, opt):
+        assert q.c_cls.shape == p.c_cls.shape and np.all(np.isfinite(q.c_cls))
+        assert not np.array_equal(q.c_cls, p.c_cls) and q.c0 == p.c0
+    srv = Server(opt, target_err=0.0, chunk=8, burn_in=4, min_steps=8, max_steps=16)
+    res = srv.run(reqs, realtime=False)
+    for req, r in zip(reqs, res):
+        e, err, _ = srv.solve_alone(req, r.steps)
+        assert e == r.e_var and err == r.e_err, (req["id"], e, r.e_var)
