@@ -822,7 +822,8 @@ static scqmc_status launch_sample(scqmc_ctx *c, long long n_steps, long long bur
     long long blk = c->opt.block_len > 0 ? c->opt.block_len : 1;
     for (long long done = 0; done < n_steps; done += blk) {
         int ns = (int)std::min(blk, n_steps - done);
-        hipLaunchKernelGGL(k_order, dim3(1), dim3(1024), 0, c->stream, c->wvirt.as<const unsigned>(), c->W, order);
+        hipLaunchKernelGGL(k_order, dim3(1), dim3(1024), 0, c->stream, c->wvirt.as<const unsigned>(), c->W, (int)c->V,
+                           order);
         if (c->opt.precision == 1)
             hipLaunchKernelGGL(k_sample<float>, dim3(grid1(c->W, WPB)), dim3(64 * WPB), lds, c->stream, P, S, order,
                                c->W, c->step + done, ns, burn_in, NL);

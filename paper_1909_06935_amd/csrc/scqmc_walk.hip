@@ -1099,8 +1099,97 @@ __device__ void order_walkers(const unsigned *virt, long long W, int *order) {
         }
     }
 }
-__global__ __launch_bounds__(1024) void k_order(const unsigned *virt, long long W, int *order) {
-    order_walkers(virt, W, order);
+
+// The single-system form also keeps L2 locality.  Workgroups are handed to
+// the eight XCDs round-robin (slot s runs on XCD s mod 8) and each XCD has its
+// own L2.  Inside each virtual-electron count the walkers are bucketed by
+// their virtual spin-orbitals (the one, or the pair), and every XCD gets a
+// contiguous run of that bucket order (its share of the count's slots, in
+// order): the walkers an XCD holds at one time then share virtual orbitals,
+// and with them most of the integrals they read.  The cost order is kept:
+// counts still run in ascending order on every XCD.  Order inside a bucket
+// follows LDS atomics, so it can differ between runs; results cannot.
+#define NXCD 8
+#define OB1 1024   // buckets of one-virtual walkers
+#define OB2 8192   // buckets of two-virtual walkers
+#define OBN 10240  // 1 + OB1 + OB2, rounded up to 10 per thread
+__device__ __forceinline__ int order_key(unsigned v, int V2, int sh1, int sh2) {
+    int c = virt_count(v);
+    unsigned v0 = v & 0xFFFFu, v1 = v >> 16;
+    if (c == 0) return 0;
+    if (c == 1) return 1 + (int)(v0 >> sh1);
+    return 1 + OB1 + (int)((v0 * (unsigned)V2 + v1) >> sh2);
+}
+__global__ __launch_bounds__(1024) void k_order(const unsigned *virt, long long W, int V, int *order) {
+    __shared__ int hist[OBN];
+    __shared__ int cur[OBN];
+    __shared__ int tot[1024];
+    int t = threadIdx.x;
+    int V2 = 2 * V, sh1 = 0, sh2 = 0;
+    while (((V2 - 1) >> sh1) >= OB1) sh1++;
+    while ((((unsigned)V2 * (unsigned)V2 - 1u) >> sh2) >= (unsigned)OB2) sh2++;
+    for (int k = t; k < OBN; k += 1024) hist[k] = 0;
+    __syncthreads();
+    for (long long i0 = t; i0 < W; i0 += 1024LL * OB) {
+        unsigned v[OB];
+#pragma unroll
+        for (int k = 0; k < OB; k++) {
+            long long i = i0 + 1024LL * k;
+            v[k] = i < W ? virt[i] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < OB; k++)
+            if (i0 + 1024LL * k < W) atomicAdd(&hist[order_key(v[k], V2, sh1, sh2)], 1);
+    }
+    __syncthreads();
+    // exclusive scan of the bucket counts, ten per thread
+    constexpr int PT = OBN / 1024;
+    int a[PT], sum = 0;
+#pragma unroll
+    for (int k = 0; k < PT; k++) { a[k] = hist[PT * t + k]; sum += a[k]; }
+    tot[t] = sum;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        int x = t >= d ? tot[t - d] : 0;
+        __syncthreads();
+        tot[t] += x;
+        __syncthreads();
+    }
+    int ex = tot[t] - sum;
+#pragma unroll
+    for (int k = 0; k < PT; k++) { cur[PT * t + k] = ex; ex += a[k]; }
+    __syncthreads();
+    // counts: 0 -> key 0, 1 -> keys [1, 1 + OB1), 2 -> [1 + OB1, OBN)
+    int S[3] = {0, cur[1], cur[1 + OB1]};
+    int n[3] = {cur[1], cur[1 + OB1] - cur[1], (int)W - cur[1 + OB1]};
+    __syncthreads();
+    for (long long i0 = t; i0 < W; i0 += 1024LL * OB) {
+        unsigned v[OB];
+#pragma unroll
+        for (int k = 0; k < OB; k++) {
+            long long i = i0 + 1024LL * k;
+            v[k] = i < W ? virt[i] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < OB; k++) {
+            long long i = i0 + 1024LL * k;
+            if (i >= W) continue;
+            int key = order_key(v[k], V2, sh1, sh2), c = virt_count(v[k]);
+            int tc = atomicAdd(&cur[key], 1) - S[c];   // rank inside the count
+            // XCD j owns the slots S_c + s' (0 <= s' < n_c) with (S_c + s') mod 8 = j:
+            // s' = r_j + 8 q, r_j = (j - S_c) mod 8, q < m_j; ranks are dealt to
+            // XCD 0, 1, ... in runs of m_j
+            int start = 0, slot = -1;
+#pragma unroll
+            for (int j = 0; j < NXCD; j++) {
+                int r = (j - S[c]) & (NXCD - 1);
+                int m = n[c] > r ? (n[c] - r + NXCD - 1) / NXCD : 0;
+                if (slot < 0 && tc < start + m) slot = S[c] + r + NXCD * (tc - start);
+                start += m;
+            }
+            order[slot] = (int)i;
+        }
+    }
 }
 
 // order: walker of each workgroup slot (a permutation of 0..W-1)
