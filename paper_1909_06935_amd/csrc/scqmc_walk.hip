@@ -401,6 +401,11 @@ __device__ double phi1(const DevProblem &P, unsigned long long y, int s, int sg,
     //   = bs + br - [(P1 < s) + (P2 < s) + (P1 < r) + (P2 < r)]
     // (symmetric in Q1, Q2).  An active P precedes the virtual s when P is
     // alpha or s is beta; s precedes r exactly when s is alpha and r beta.
+    // With a wave-uniform group (U) the list entries are scalars: the
+    // integrals of eight entries are requested before any is used, so their
+    // loads overlap (J and K are both read; the spin conditions select
+    // afterwards).  Same order of additions as one entry at a time.
+    constexpr int P1UNR = (U ? 8 : 1);
     for (int li = 1; li <= nl; li++) {
         uint2 ox = lists(li);
         unsigned cnt = ox.y & 0xFFFFFFu;
@@ -411,7 +416,39 @@ __device__ double phi1(const DevProblem &P, unsigned long long y, int s, int sg,
         bool s_first = (sg == 0) && (sr == 1);
         unsigned rr = (unsigned)(r & 31);
         unsigned long long yr = y & ~(1ull << r);
-        for (unsigned k = 0; k < cnt; k++) {
+        unsigned k = 0;
+        if (P1UNR > 1) {
+            for (; k + P1UNR <= cnt; k += P1UNR) {
+                unsigned cd[P1UNR];
+                double wv[P1UNR];
+                R Jv[P1UNR], Kv[P1UNR];
+#pragma unroll
+                for (int j = 0; j < P1UNR; j++) {
+                    cd[j] = tload<U>(P.xtab.codes, ox.x + k + j);
+                    wv[j] = tload<U>(P.xtab.vals, ox.x + k + j);
+                }
+#pragma unroll
+                for (int j = 0; j < P1UNR; j++) {
+                    unsigned q1 = (cd[j] >> 6) & 31u, q2 = cd[j] & 31u;
+                    Jv[j] = E[q2 * N3 + rr * N2 + q1 * Np + sp];
+                    Kv[j] = E[q1 * N3 + rr * N2 + q2 * Np + sp];
+                }
+#pragma unroll
+                for (int j = 0; j < P1UNR; j++) {
+                    int t = (int)(cd[j] >> 6), u = (int)(cd[j] & 63u);
+                    if (t == r || u == r) continue;
+                    int P1 = g_of_active(P, t), P2 = g_of_active(P, u);
+                    int st = t >> 5, su = u >> 5;
+                    int br = key_below(yr | (1ull << t) | (1ull << u), r);
+                    int e = bs + br - ((st == 0 || sg == 1) + (su == 0 || sg == 1) + (P1 < gr) + (P2 < gr));
+                    R J = (st == sg && su == sr) ? Jv[j] : R(0);
+                    R K = (su == sg && st == sr) ? Kv[j] : R(0);
+                    double el = (double)(s_first ? J - K : K - J);
+                    acc += (e & 1) ? -wv[j] * el : wv[j] * el;
+                }
+            }
+        }
+        for (; k < cnt; k++) {
             unsigned code = tload<U>(P.xtab.codes, ox.x + k);
             int t = (int)(code >> 6), u = (int)(code & 63u);
             if (t == r || u == r) continue;
@@ -440,16 +477,52 @@ __device__ __forceinline__ double phi2(const DevProblem &P, int s1, int s2, uint
     unsigned a1 = (unsigned)(P.A + s1 - sg1 * P.V), a2 = (unsigned)(P.A + s2 - sg2 * P.V);
     const R *E = Ints<R>::eri(P) + (a1 * Np) * Np + a2;
     double acc = 0.0;
+    // wave-uniform group: four entries' integrals in flight at a time (same
+    // order of additions)
+    constexpr int PU = (U ? 4 : 1);
+    unsigned k = 0;
     if (sg1 != sg2) {
         // alpha-beta pair: only (s1 t|s2 u) survives; spin part of the phase (-1)^(n_beta + 1)
-        for (unsigned k = 0; k < ox.y; k++) {
+        for (; k + PU <= ox.y; k += PU) {
+            unsigned c[PU];
+            double w[PU];
+            R e[PU];
+#pragma unroll
+            for (int j = 0; j < PU; j++) {
+                c[j] = tload<U>(P.xtab.codes, ox.x + k + j);
+                w[j] = tload<U>(P.xtab.vals, ox.x + k + j);
+            }
+#pragma unroll
+            for (int j = 0; j < PU; j++) e[j] = E[((c[j] >> 6) & 31u) * N3 + (c[j] & 31u) * Np];
+#pragma unroll
+            for (int j = 0; j < PU; j++) acc += w[j] * (double)e[j];
+        }
+        for (; k < ox.y; k++) {
             unsigned code = tload<U>(P.xtab.codes, ox.x + k);
             unsigned t = (code >> 6) & 31u, u = code & 31u;
             acc += tload<U>(P.xtab.vals, ox.x + k) * (double)E[t * N3 + u * Np];
         }
         return ((P.neb + 1) & 1) ? -acc : acc;
     }
-    for (unsigned k = 0; k < ox.y; k++) {
+    for (; k + PU <= ox.y; k += PU) {
+        unsigned c[PU];
+        double w[PU];
+        R e1[PU], e2[PU];
+#pragma unroll
+        for (int j = 0; j < PU; j++) {
+            c[j] = tload<U>(P.xtab.codes, ox.x + k + j);
+            w[j] = tload<U>(P.xtab.vals, ox.x + k + j);
+        }
+#pragma unroll
+        for (int j = 0; j < PU; j++) {
+            unsigned t = (c[j] >> 6) & 31u, u = c[j] & 31u;
+            e1[j] = E[t * N3 + u * Np];
+            e2[j] = E[u * N3 + t * Np];
+        }
+#pragma unroll
+        for (int j = 0; j < PU; j++) acc += w[j] * (double)(e1[j] - e2[j]);
+    }
+    for (; k < ox.y; k++) {
         unsigned code = tload<U>(P.xtab.codes, ox.x + k);
         unsigned t = (code >> 6) & 31u, u = code & 31u;
         acc += tload<U>(P.xtab.vals, ox.x + k) * (double)(E[t * N3 + u * Np] - E[u * N3 + t * Np]);
