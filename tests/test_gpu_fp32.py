@@ -76,6 +76,23 @@ def test_fp32_eval_cfg2_snapshot():
     _check(prob, sample_by_class(orc, prob.space, prob.ref_dets, 12, 2024), "cfg2 fp32")
 
 
+def test_fp32_eval_cfg3_snapshot():
+    """100 orbitals, CAS(14,14): first-order-space determinants (nonzero-psi
+    neighbours of a reference determinant).  The rounding bound holds for
+    every one; the median is checked against 2e-5 Eh, as the terms of a
+    local energy are more and larger here than at 12 and 40 orbitals."""
+    prob = wl.make_problem("cfg3")
+    prob.eps_virt = np.linspace(1.0, 3.0, prob.space.n_virt)
+    prob.e0_ref = 0.0
+    _say("cfg3 fp32 snapshot")
+    from paper_1909_06935_amd.scqmc import Engine
+    g = Engine.from_problem(prob, mode=0).debug_neighbors(prob.ref_dets[len(prob.ref_dets) // 3])
+    nz = np.nonzero(g["psi"] != 0)[0]
+    rng = np.random.Generator(np.random.PCG64(17))
+    dets = g["dets"][rng.choice(nz, size=12, replace=False)]
+    _check(prob, dets, "cfg3 fp32", median_bar=2e-5)
+
+
 def test_fp32_walk_statistics_cfg1():
     prob = cfg1_problem()
     _say("cfg1 fp32 walk")

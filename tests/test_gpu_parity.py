@@ -212,3 +212,54 @@ def test_walker_psi_every_class(which):
 def _vc(space, d):
     from helpers import virtual_count
     return virtual_count(space, d)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_cfg2_bench_launch_sampled_walkers(precision):
+    """The benchmark's launch configuration at full size (40 orbitals,
+    16,384 walkers, SC-NEVPT2 mode, walkers dispatched in cost order): after
+    one step from an equilibrated state, 96 sampled walkers are compared with
+    the oracle walking the same walker (same id, seed and step) alone: the new
+    determinant exactly, psi and the step's residence-time sums t, t E_L,
+    t_0.  In the FP32 form the move is compared where the oracle's own clocks
+    are not within the FP32 rounding of each other (near-ties may differ)."""
+    prob = wl.make_problem("cfg2")
+    prob.eps_virt = np.linspace(1.0, 3.0, prob.space.n_virt)
+    prob.e0_ref = float(np.load(wl.reference_file("cfg2"))["e_cas"])
+    W = wl.CONFIGS["cfg2"]["walkers"]
+    assert W == 16384
+    _say(f"cfg2 full launch, precision {precision}")
+    warm = engine_for(prob, mode=1, burn_in=0, block_len=1)
+    warm.init_walkers(wl.draw_walkers(prob.ref_dets, prob.ref_coeff, W, prob.seed_walk), prob.seed_walk)
+    warm.sample(40)
+    s0, _ = warm.read_walkers()
+    eng = engine_for(prob, mode=1, burn_in=0, block_len=1)
+    if precision:
+        eng.set_options(mode=1, precision=1, burn_in=0, block_len=1)
+    seed = 777
+    eng.init_walkers(s0, seed)
+    eng.sample(1)
+    gd, gpsi = eng.read_walkers()
+    gws = eng.read_walker_sums()
+    steps, bad = eng.read_counters()
+    assert steps == 1 and bad == 0
+    orc = O.Oracle.from_problem(prob, mode=1)
+    rng = np.random.Generator(np.random.PCG64(11))
+    idx = np.sort(rng.choice(W, size=96, replace=False))
+    moved_same = close = 0
+    for i in idx:
+        od, opsi, ows, _, stuck = orc.run(s0[i:i + 1], seed, 1, step0=0, burn_in=0, wid0=int(i))
+        assert stuck == 0
+        same = np.array_equal(gd[i], od[0])
+        if precision == 0:
+            assert same, i
+            assert abs(gpsi[i] - opsi[0]) <= 1e-11 * abs(opsi[0]), (i, gpsi[i], opsi[0])
+            assert np.allclose(gws[i], ows[0], rtol=1e-10, atol=1e-12), (i, gws[i], ows[0])
+        else:
+            # t and t E_L from FP32 terms: relative errors of order 1e-6,
+            # larger for walkers near a node of psi (large kappa)
+            close += bool(np.allclose(gws[i], ows[0], rtol=1e-5, atol=1e-8))
+            assert np.allclose(gws[i], ows[0], rtol=1e-2, atol=1e-6), (i, gws[i], ows[0])
+        moved_same += same
+    if precision:
+        assert moved_same >= 90 and close >= 85, (moved_same, close)
