@@ -35,6 +35,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+# wave64 VALU instructions per second: 256 CUs x 4 SIMDs x 2.4 GHz, one
+# wave64 instruction per SIMD every 4 cycles (16 lanes per cycle)
+VALU_PEAK_WAVE_INSTR = 256 * 4 * 2.4e9 / 4
 WALKER_STATE_BYTES = 2 * (8 + 4 + 8 + 24)   # key, virtual codes, psi, per-walker sums; read + write
 
 WORKLOADS = {
@@ -123,6 +126,26 @@ def measured_traffic(config, walker_steps):
     if int(kv.get("walker_steps_per_launch", -1)) != walker_steps:
         return None
     return float(kv["traffic_bytes_per_launch"])
+
+
+def measured_valu(config, walker_steps):
+    """VALU / SALU wave instructions per launch from the committed counter
+    summary (same conditions as measured_traffic), or None."""
+    path = os.path.join(ROOT, "profiles", f"k_sample_{config}_valu_counters.md")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            parts = line.strip().split(":", 1)
+            if len(parts) == 2 and parts[0] in ("source_digest", "valu_insts_per_launch", "salu_insts_per_launch",
+                                                "walker_steps_per_launch"):
+                kv[parts[0]] = parts[1].strip()
+    if kv.get("source_digest") != kernel_source_digest():
+        return None
+    if int(kv.get("walker_steps_per_launch", -1)) != walker_steps:
+        return None
+    return float(kv["valu_insts_per_launch"]), float(kv["salu_insts_per_launch"])
 
 
 def main():
@@ -241,6 +264,12 @@ def main():
             "fp64": {"achieved": fl, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": fl / FP64_PEAK_TFLOPS,
                      "flops_per_walker_step": per_flops},
         }
+        vi = measured_valu(args.config, W * args.block)
+        if vi is not None:
+            va = vi[0] / avg_s
+            out["roofline"]["valu"] = {"achieved": va, "peak": VALU_PEAK_WAVE_INSTR, "unit": "wave64 instr/s",
+                                       "frac": va / VALU_PEAK_WAVE_INSTR,
+                                       "salu_frac": vi[1] / avg_s / (256 * 2.4e9)}
         out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
