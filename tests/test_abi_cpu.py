@@ -54,3 +54,14 @@ def test_missing_library_is_loud(tmp_path, monkeypatch):
     monkeypatch.setattr(scqmc, "_lib", None)
     with pytest.raises(ImportError):
         scqmc.lib()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asked for more it exits with a message
+    before touching a device."""
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
