@@ -194,7 +194,10 @@ scqmc_status scqmc_init_walkers(scqmc_ctx *ctx, int64_t n_walkers, const uint64_
  * neighbour set, accumulates the estimators with residence weight
  * t = 1/sum of rates once the global step index reaches burn_in, and moves
  * the walker by the two-level first-reaction method (group of neighbours
- * sharing an active part, then one neighbour within it). */
+ * sharing an active part, then one neighbour within it).  Before every
+ * launch the walkers are put in a dispatch order (costliest class first,
+ * grouped by virtual orbitals); a walker's chain depends only on its id, the
+ * seed and the step, so the order never changes a result. */
 scqmc_status scqmc_sample(scqmc_ctx *ctx, int64_t n_steps);
 scqmc_status scqmc_synchronize(scqmc_ctx *ctx);
 
