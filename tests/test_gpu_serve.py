@@ -45,3 +45,26 @@ def test_serve_with_optimised_templates():
     for req, r in zip(reqs, res):
         e, err, _ = srv.solve_alone(req, r.steps)
         assert e == r.e_var and err == r.e_err, (req["id"], e, r.e_var)
+
+
+@pytest.mark.parametrize("name", ["cfg2", "cfg3"])
+def test_footprint_bounds_device_memory(name):
+    """Admission by HBM footprint: the device memory a context holds once set
+    up (integrals, tables, walkers) stays within footprint_bytes, the figure
+    the server admits requests by (checked on the 40- and 100-orbital
+    systems, large enough for the allocator's rounding not to matter)."""
+    import torch
+    from paper_1909_06935_amd.scqmc import Engine
+    from paper_1909_06935_amd.serve import footprint_bytes
+    prob = wl.make_problem(name)
+    prob.n_walkers = wl.CONFIGS[name]["walkers"]
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    eng = Engine.from_problem(prob, mode=0)
+    eng.init_walkers(wl.draw_walkers(prob.ref_dets, prob.ref_coeff, prob.n_walkers, prob.seed_walk), prob.seed_walk)
+    eng.synchronize()
+    used = free0 - torch.cuda.mem_get_info()[0]
+    fp = footprint_bytes(prob)
+    _say(f"{name}: resident {used / 2**20:.1f} MiB, footprint {fp / 2**20:.1f} MiB")
+    assert 0 < used <= fp + (32 << 20), (used, fp)
+    eng.close()
