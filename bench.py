@@ -159,6 +159,8 @@ def main():
     ap.add_argument("--target-err", type=float, default=1e-2, help="serve: target E_var error (Eh)")
     ap.add_argument("--max-steps", type=int, default=10000, help="serve: step cap per request")
     ap.add_argument("--no-opt", action="store_true", help="serve: keep the templates' random SC coefficients")
+    ap.add_argument("--alone-every", type=int, default=1,
+                    help="serve: walk every k-th request alone as well (plain kernel, same steps) for the comparison")
     ap.add_argument("--hbm-gib", type=int, default=64, help="serve: device memory budget for admitted requests")
     ap.add_argument("--walkers", type=int, default=0)
     ap.add_argument("--block", type=int, default=1, help="steps per kernel launch")
@@ -264,6 +266,10 @@ def main():
             "fp64": {"achieved": fl, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": fl / FP64_PEAK_TFLOPS,
                      "flops_per_walker_step": per_flops},
         }
+        tr = out["roofline"]["traffic"]
+        if tr is not None:
+            # measured fabric bytes over the same launch time: the third fraction
+            out["roofline"]["traffic_frac"] = tr / avg_s / (HBM_PEAK_GBS * 1e9)
         vi = measured_valu(args.config, W * args.block)
         if vi is not None:
             va = vi[0] / avg_s
@@ -347,12 +353,18 @@ def run_serve(args):
     ws = sum(r.steps * r.walkers for r in res)
     serial = 0.0
     dev = 0.0
+    ws_alone = 0
+    n_alone = 0
     for k, (req, r) in enumerate(zip(reqs, res)):
+        if k % args.alone_every:
+            continue
         e, err, dt = srv.solve_alone(req, r.steps)
         serial += dt
+        ws_alone += r.steps * r.walkers
+        n_alone += 1
         dev = max(dev, abs(e - r.e_var))
-        if k % 10 == 9:
-            print(f"# alone: {k + 1} requests, {serial:.1f} s", file=sys.stderr, flush=True)
+        if n_alone % 10 == 0:
+            print(f"# alone: {n_alone} requests, {serial:.1f} s", file=sys.stderr, flush=True)
     out = {
         "metric": "walker-steps/s (serving loop); p50/p99 time-to-target-error", "value": ws / wall,
         "unit": "walker-steps/s", "n_gpus": 1, "steps": int(sum(r.steps for r in res)), "warmup": 0,
@@ -368,7 +380,8 @@ def run_serve(args):
         "steps_p50": float(np.percentile([r.steps for r in res], 50)),
         "template_prep_s": float(sum(prep)),
         "achieved_err_max": float(max(r.e_err for r in res)),
-        "wall_s": wall, "serial_plain_gpu_s": serial, "serial_plain_value": ws / serial,
+        "wall_s": wall, "alone_checked": n_alone, "serial_plain_gpu_s": serial,
+        "serial_plain_value": ws_alone / serial,
         "max_abs_diff_mix_vs_alone": dev,
     }
     print(json.dumps(out), flush=True)
