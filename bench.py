@@ -321,7 +321,8 @@ def run_batch(args):
                                "references, 256-8192 walkers each, SC-MRCI + SC-NEVPT2 mode",
                    "walkers": sum(p.n_walkers for p in systems)},
         "serial_plain_value": ws / serial, "speedup_vs_serial": serial / batched,
-        "schedule": {"order": order, "steps_per_launch": spl},
+        "schedule": {"order": order, "steps_per_launch": spl,
+                     "hand_out": "hardware dispatch" if b.bin == 0 else f"persistent grid, bins of {b.bin} slots"},
     }
     print(json.dumps(out), flush=True)
 

@@ -257,7 +257,9 @@ scqmc_status scqmc_load_state(scqmc_ctx *ctx, const void *buf, int64_t len);
  * launch per group of steps.  A schedule maps workgroups to (system, walker);
  * a walker's chain depends only on its own id and its system's step counter,
  * so the results equal those of the systems walked one by one, bit for bit.
- * The launch and the step advance are captured in a HIP graph and replayed.
+ * The launch and the step advance are captured in a HIP graph and replayed
+ * (with the persistent hand-out, the work counter is cleared by the step
+ * advance, so replays need no memset).
  * The batch keeps pointers to the contexts (which must outlive it) and reads
  * their current state at every call.
  * ------------------------------------------------------------------------ */
@@ -272,11 +274,18 @@ scqmc_status scqmc_batch_sample(scqmc_batch *batch, int64_t n_steps);
 /* Schedule: order 0 = systems one after another, 1 = walkers of all systems
  * interleaved, 2 = costliest systems first; steps_per_launch 1..1024. */
 scqmc_status scqmc_batch_set_schedule(scqmc_batch *batch, int32_t order, int32_t steps_per_launch);
+/* Hand-out of the schedule's slots: bin = 0 lets the hardware dispatch one
+ * workgroup per slot; bin >= 1 launches a persistent grid (sixteen
+ * workgroups per compute unit) whose waves take work items of bin
+ * consecutive slots from a device counter until the schedule is exhausted.
+ * Results are the same either way.  bin 0..4096, else INVALID_ARG. */
+scqmc_status scqmc_batch_set_queue(scqmc_batch *batch, int32_t bin);
 /* Autotuner: times trial_steps steps (real steps of every system) for each
- * order 0..2 and 1, 2, 4 steps per launch and keeps the fastest; outputs the
- * choice and its time per step (each optional). */
+ * order 0..2, 1, 2, 4 steps per launch and hand-out bin 0 (hardware), 1, 4
+ * (persistent) and keeps the fastest; outputs the choice and its time per
+ * step (each optional). */
 scqmc_status scqmc_batch_tune(scqmc_batch *batch, int64_t trial_steps, int32_t *order, int32_t *steps_per_launch,
-                              double *ms_per_step);
+                              int32_t *bin, double *ms_per_step);
 
 #ifdef __cplusplus
 }

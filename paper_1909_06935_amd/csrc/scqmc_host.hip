@@ -1299,14 +1299,17 @@ struct scqmc_batch {
     int precision = 0;
     int order = 0;          // 0: system by system, 1: walkers interleaved, 2: costliest systems first
     int spl = 1;            // steps per launch
+    int bin = 0;            // 0: hardware dispatch of the slots; >= 1: persistent grid, work items of bin slots
+    int ncu = 0;            // compute units of the device (persistent grid size)
     long long nslots = 0;
     std::vector<long long> Ws;
     int sched_order = -1;
     DBuf dsys, dslot_sys, dslot_w;
+    DBuf dhead;             // work counter of the persistent form (zero between launches)
     size_t lds = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
-    int graph_spl = 0;
+    int graph_spl = 0, graph_bin = -1;
     long long graph_slots = -1;
 };
 
@@ -1417,6 +1420,12 @@ scqmc_status batch_upload(scqmc_batch *b) {
         free_graph(b);
     }
     BHIP(b, hipMemcpy(b->dsys.p, hs.data(), sizeof(BatchSys) * n, hipMemcpyHostToDevice));
+    if (!b->dhead.p) {
+        if (hipMalloc(&b->dhead.p, sizeof(unsigned)) != hipSuccess) BFAIL(b, SCQMC_E_OOM, "work counter");
+        b->dhead.n = sizeof(unsigned);
+        BHIP(b, hipMemset(b->dhead.p, 0, sizeof(unsigned)));
+        BHIP(b, hipDeviceSynchronize());
+    }
     b->lds = WPB * wave_lds_bytes(NLmax);
     return SCQMC_OK;
 }
@@ -1424,6 +1433,24 @@ scqmc_status batch_upload(scqmc_batch *b) {
 scqmc_status batch_launch(scqmc_batch *b, int nsteps) {
     int n = (int)b->ctx.size();
     dim3 grid(grid1(b->nslots, WPB)), blk(64 * WPB);
+    if (b->bin > 0) {
+        // persistent grid: sixteen workgroups (four waves per SIMD) per compute unit
+        long long items = (b->nslots + b->bin - 1) / b->bin;
+        long long g = std::min<long long>(items, 16LL * std::max(1, b->ncu));
+        hipLaunchKernelGGL(k_order_batch, dim3(n), dim3(1024), 0, b->stream, b->dsys.as<const BatchSys>());
+        if (b->precision == 1)
+            hipLaunchKernelGGL(k_sample_batch_queue<float>, dim3((unsigned)g), blk, b->lds, b->stream,
+                               b->dsys.as<const BatchSys>(), b->dslot_sys.as<const int>(), b->dslot_w.as<const int>(),
+                               b->nslots, nsteps, b->dhead.as<unsigned>(), b->bin);
+        else
+            hipLaunchKernelGGL(k_sample_batch_queue<double>, dim3((unsigned)g), blk, b->lds, b->stream,
+                               b->dsys.as<const BatchSys>(), b->dslot_sys.as<const int>(), b->dslot_w.as<const int>(),
+                               b->nslots, nsteps, b->dhead.as<unsigned>(), b->bin);
+        hipLaunchKernelGGL(k_batch_advance, dim3(grid1(n, 64)), dim3(64), 0, b->stream, b->dsys.as<BatchSys>(), n,
+                           nsteps, b->dhead.as<unsigned>());
+        BHIP(b, hipGetLastError());
+        return SCQMC_OK;
+    }
     hipLaunchKernelGGL(k_order_batch, dim3(n), dim3(1024), 0, b->stream, b->dsys.as<const BatchSys>());
     if (b->precision == 1)
         hipLaunchKernelGGL(k_sample_batch<float>, grid, blk, b->lds, b->stream, b->dsys.as<const BatchSys>(),
@@ -1431,7 +1458,8 @@ scqmc_status batch_launch(scqmc_batch *b, int nsteps) {
     else
         hipLaunchKernelGGL(k_sample_batch<double>, grid, blk, b->lds, b->stream, b->dsys.as<const BatchSys>(),
                            b->dslot_sys.as<const int>(), b->dslot_w.as<const int>(), b->nslots, nsteps);
-    hipLaunchKernelGGL(k_batch_advance, dim3(grid1(n, 64)), dim3(64), 0, b->stream, b->dsys.as<BatchSys>(), n, nsteps);
+    hipLaunchKernelGGL(k_batch_advance, dim3(grid1(n, 64)), dim3(64), 0, b->stream, b->dsys.as<BatchSys>(), n, nsteps,
+                       (unsigned *)nullptr);
     BHIP(b, hipGetLastError());
     return SCQMC_OK;
 }
@@ -1439,7 +1467,7 @@ scqmc_status batch_launch(scqmc_batch *b, int nsteps) {
 // one graph per (steps per launch, schedule): a batched launch and the step
 // advance, replayed as many times as needed
 scqmc_status batch_graph(scqmc_batch *b) {
-    if (b->gexec && b->graph_spl == b->spl && b->graph_slots == b->nslots) return SCQMC_OK;
+    if (b->gexec && b->graph_spl == b->spl && b->graph_slots == b->nslots && b->graph_bin == b->bin) return SCQMC_OK;
     free_graph(b);
     BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     scqmc_status st = batch_launch(b, b->spl);
@@ -1451,6 +1479,7 @@ scqmc_status batch_graph(scqmc_batch *b) {
     BHIP(b, hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
     b->graph_spl = b->spl;
     b->graph_slots = b->nslots;
+    b->graph_bin = b->bin;
     return SCQMC_OK;
 }
 
@@ -1493,7 +1522,9 @@ scqmc_status scqmc_batch_create(scqmc_ctx *const *ctxs, int32_t n, scqmc_batch *
     b->device = dev;
     b->ctx.assign(ctxs, ctxs + n);
     b->precision = ctxs[0]->opt.precision;
-    if (hipSetDevice(dev) != hipSuccess || hipStreamCreate(&b->stream) != hipSuccess) {
+    if (hipSetDevice(dev) != hipSuccess || hipStreamCreate(&b->stream) != hipSuccess ||
+        hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        if (b->stream) hipStreamDestroy(b->stream);
         delete b;
         return SCQMC_E_DEVICE;
     }
@@ -1509,6 +1540,7 @@ void scqmc_batch_destroy(scqmc_batch *b) {
     b->dsys.release();
     b->dslot_sys.release();
     b->dslot_w.release();
+    b->dhead.release();
     if (b->stream) hipStreamDestroy(b->stream);
     delete b;
 }
@@ -1524,32 +1556,37 @@ scqmc_status scqmc_batch_sample(scqmc_batch *b, int64_t n_steps) {
 }
 
 scqmc_status scqmc_batch_tune(scqmc_batch *b, int64_t trial_steps, int32_t *order, int32_t *steps_per_launch,
-                              double *ms_per_step) {
+                              int32_t *bin, double *ms_per_step) {
     if (!b) return SCQMC_E_INVALID_ARG;
     if (trial_steps <= 0) BFAIL(b, SCQMC_E_INVALID_ARG, "trial_steps must be positive");
     BHIP(b, hipSetDevice(b->device));
     b->precision = b->ctx[0]->opt.precision;
-    const int orders[3] = {0, 1, 2}, spls[3] = {1, 2, 4};
+    const int orders[3] = {0, 1, 2}, spls[3] = {1, 2, 4}, bins[3] = {0, 1, 4};
     double best = 1e300;
-    int bo = 0, bs = 1;
+    int bo = 0, bs = 1, bb = 0;
     for (int o : orders)
-        for (int sp : spls) {
-            b->order = o;
-            b->spl = sp;
-            long long nst = ((trial_steps + sp - 1) / sp) * sp;
-            // untimed first call builds the schedule and the graph
-            scqmc_status st = batch_run(b, sp);
-            if (st != SCQMC_OK) return st;
-            auto t0 = std::chrono::steady_clock::now();
-            st = batch_run(b, nst);
-            if (st != SCQMC_OK) return st;
-            double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / nst;
-            if (ms < best) { best = ms; bo = o; bs = sp; }
-        }
+        for (int sp : spls)
+            for (int bn : bins) {
+                b->order = o;
+                b->spl = sp;
+                b->bin = bn;
+                long long nst = ((trial_steps + sp - 1) / sp) * sp;
+                // untimed first call builds the schedule and the graph
+                scqmc_status st = batch_run(b, sp);
+                if (st != SCQMC_OK) return st;
+                auto t0 = std::chrono::steady_clock::now();
+                st = batch_run(b, nst);
+                if (st != SCQMC_OK) return st;
+                double ms =
+                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / nst;
+                if (ms < best) { best = ms; bo = o; bs = sp; bb = bn; }
+            }
     b->order = bo;
     b->spl = bs;
+    b->bin = bb;
     if (order) *order = bo;
     if (steps_per_launch) *steps_per_launch = bs;
+    if (bin) *bin = bb;
     if (ms_per_step) *ms_per_step = best;
     return SCQMC_OK;
 }
@@ -1560,6 +1597,13 @@ scqmc_status scqmc_batch_set_schedule(scqmc_batch *b, int32_t order, int32_t ste
         BFAIL(b, SCQMC_E_INVALID_ARG, "order must be 0..2, steps_per_launch 1..1024");
     b->order = order;
     b->spl = steps_per_launch;
+    return SCQMC_OK;
+}
+
+scqmc_status scqmc_batch_set_queue(scqmc_batch *b, int32_t bin) {
+    if (!b) return SCQMC_E_INVALID_ARG;
+    if (bin < 0 || bin > 4096) BFAIL(b, SCQMC_E_INVALID_ARG, "bin must be 0..4096");
+    b->bin = bin;
     return SCQMC_OK;
 }
 

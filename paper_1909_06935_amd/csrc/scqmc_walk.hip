@@ -1322,11 +1322,47 @@ __global__ __launch_bounds__(64 * WPB, 4) void k_sample_batch(const BatchSys *sy
     sample_walker<R>(P, S, Wn, w, st0, nsteps, bi, L, lane);
 }
 
+// Persistent form of the batched launch: a grid of about as many workgroups
+// as the GPU holds at once, whose waves take work items -- bins of `bin`
+// consecutive schedule slots -- from a device counter until the schedule is
+// exhausted (every wave leaves at the first item past the end).  The slots
+// are the same as in k_sample_batch; only the hand-out is dynamic.
+template <class R>
+__global__ __launch_bounds__(64 * WPB, 4) void k_sample_batch_queue(const BatchSys *sys, const int *slot_sys,
+                                                               const int *slot_w, long long nslots, int nsteps,
+                                                               unsigned *head, int bin) {
+    extern __shared__ unsigned char smem[];
+    int wave = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    while (true) {
+        unsigned it = 0;
+        if (lane == 0) it = atomicAdd(head, 1u);
+        it = uni((unsigned)__shfl((int)it, 0));
+        long long s0 = (long long)it * bin;
+        if (s0 >= nslots) break;
+        long long s1 = min(nslots, s0 + (long long)bin);
+        for (long long slot = s0; slot < s1; slot++) {
+            int s = uni(slot_sys[slot]);
+            const BatchSys &B = sys[s];
+            long long w = (long long)uni(B.order[slot_w[slot]]);
+            DevProblem P = B.P;
+            WalkerArrays S = B.S;
+            int NL = uni(B.NL);
+            WaveLDS L = carve(smem + wave * wave_lds_bytes(NL), NL);
+            long long Wn = (long long)uni((unsigned long long)B.W), st0 = (long long)uni((unsigned long long)B.step0);
+            long long bi = (long long)uni((unsigned long long)B.burn_in);
+            sample_walker<R>(P, S, Wn, w, st0, nsteps, bi, L, lane);
+            __syncwarp();
+        }
+    }
+}
+
 // step counters of every system advance after a batched launch (kept on the
-// device so that a captured graph of launches can be replayed as is)
-__global__ void k_batch_advance(BatchSys *sys, int nsys, int nsteps) {
+// device so that a captured graph of launches can be replayed as is); the
+// work counter of the persistent form is cleared for the next launch
+__global__ void k_batch_advance(BatchSys *sys, int nsys, int nsteps, unsigned *head) {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s < nsys) sys[s].step0 += nsteps;
+    if (s == 0 && head) *head = 0u;
 }
 
 // local energies without moving (parity / snapshots)

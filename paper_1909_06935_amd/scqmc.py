@@ -108,7 +108,8 @@ def lib():
             "scqmc_batch_last_error": ([P], C.c_char_p),
             "scqmc_batch_sample": ([P, i64], C.c_int),
             "scqmc_batch_set_schedule": ([P, i32, i32], C.c_int),
-            "scqmc_batch_tune": ([P, i64, C.POINTER(i32), C.POINTER(i32), C.POINTER(dbl)], C.c_int),
+            "scqmc_batch_set_queue": ([P, i32], C.c_int),
+            "scqmc_batch_tune": ([P, i64, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(dbl)], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -370,7 +371,14 @@ class Batch:
     def set_schedule(self, order, steps_per_launch):
         self._check(lib().scqmc_batch_set_schedule(self.h, int(order), int(steps_per_launch)))
 
+    def set_queue(self, bin_slots):
+        self._check(lib().scqmc_batch_set_queue(self.h, int(bin_slots)))
+
     def tune(self, trial_steps):
-        o, sp, ms = C.c_int32(), C.c_int32(), C.c_double()
-        self._check(lib().scqmc_batch_tune(self.h, int(trial_steps), C.byref(o), C.byref(sp), C.byref(ms)))
+        """Returns (order, steps_per_launch, ms_per_step); the chosen hand-out
+        bin is kept in self.bin."""
+        o, sp, bn, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
+        self._check(lib().scqmc_batch_tune(self.h, int(trial_steps), C.byref(o), C.byref(sp), C.byref(bn),
+                                           C.byref(ms)))
+        self.bin = bn.value
         return o.value, sp.value, ms.value

@@ -1,6 +1,7 @@
 """Batched form: systems of different sizes walked by one launch give,
 bit for bit, the walk each system takes alone (any schedule, any number of
-steps per launch, graph replays included)."""
+steps per launch, hardware or persistent hand-out of the slots, graph
+replays included)."""
 import sys
 
 import numpy as np
@@ -60,10 +61,14 @@ def test_batch_equals_alone(precision):
         alone.append(_state(e))
     engines = [_fresh(prob, W, precision) for prob, W in systems]
     b = Batch(engines)
-    b.set_schedule(1, 4)      # interleaved, graph of 4-step launches (2 replays + remainder)
-    b.sample(11)
-    b.set_schedule(2, 3)      # costliest first
-    b.sample(9)
+    b.set_schedule(1, 4)      # interleaved, graph of 4-step launches (1 replay + remainder)
+    b.sample(7)
+    b.set_schedule(2, 3)      # costliest first, persistent grid taking one slot at a time
+    b.set_queue(1)
+    b.sample(6)
+    b.set_schedule(0, 2)      # system by system, persistent grid taking bins of 4 slots
+    b.set_queue(4)
+    b.sample(7)
     for i, e in enumerate(engines):
         _same(alone[i], _state(e), f"system {i}")
 
@@ -74,8 +79,8 @@ def test_batch_autotune_then_sample():
     engines = [_fresh(prob, W) for prob, W in systems]
     b = Batch(engines)
     order, spl, ms = b.tune(4)
-    _say("tuned", order, spl, ms)
-    assert order in (0, 1, 2) and spl in (1, 2, 4) and ms > 0
+    _say("tuned", order, spl, b.bin, ms)
+    assert order in (0, 1, 2) and spl in (1, 2, 4) and b.bin in (0, 1, 4) and ms > 0
     b.sample(6)
     steps = engines[0].read_counters()[0]
     for i, (prob, W) in enumerate(systems):
