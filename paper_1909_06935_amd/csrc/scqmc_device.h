@@ -63,12 +63,13 @@ __device__ __forceinline__ unsigned long long scq_hash(unsigned long long k) {
 // Open-addressing lookup (linear probing, one 16-byte load per probe).
 // Returns the (offset, count) of the key's entry list, count 0 when absent.
 __device__ __forceinline__ uint2 table_find(const DevTable &t, unsigned long long key) {
-    unsigned long long slot = scq_hash(key) & t.mask;
+    unsigned m = (unsigned)t.mask;   // capacities stay below 2^32
+    unsigned slot = (unsigned)scq_hash(key) & m;
     while (true) {
         ulonglong2 s = t.slots[slot];
         if (s.x == key) return make_uint2((unsigned)s.y, (unsigned)(s.y >> 32));
         if (s.x == SCQ_EMPTY_KEY) return make_uint2(0u, 0u);
-        slot = (slot + 1) & t.mask;
+        slot = (slot + 1u) & m;
     }
 }
 

@@ -390,6 +390,8 @@ static scqmc_status build_table(scqmc_ctx *c, int mode, const DBuf &rkeys, long 
     scratch.release();
     unsigned long long cap = 64;
     while (cap < 4ull * U) cap <<= 1;
+    // device probes use 32-bit slot indices
+    if (cap > (1ull << 32)) FAIL(c, SCQMC_E_UNSUPPORTED, "hash table of more than 2^32 slots");
     t.cap = cap;
     t.unique = U;
     TRY(dalloc(c, cnt, sizeof(unsigned) * cap));

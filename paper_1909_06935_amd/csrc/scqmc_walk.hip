@@ -109,7 +109,7 @@ struct Block {
     int nra, npa;
     unsigned fam_end[4]; // cumulative rows per kept subset of the walker's virtual electrons
     unsigned R;          // rows per group
-    long long ng, npk;   // groups, choices of Pa
+    unsigned ng, npk;    // groups, choices of Pa
 };
 
 __device__ __forceinline__ unsigned binom012(int n, int k) {
@@ -130,14 +130,14 @@ __device__ __forceinline__ void pair_decode(unsigned k, int &i, int &j) {
 
 __device__ __forceinline__ int kind_a(int k) { return (k == 1 || k == 4) ? 1 : (k == 3 ? 2 : 0); }
 __device__ __forceinline__ int kind_b(int k) { return (k == 2 || k == 4) ? 1 : (k == 5 ? 2 : 0); }
-__device__ __forceinline__ long long kind_count(int k, int a, int b) {
+__device__ __forceinline__ unsigned kind_count(int k, int a, int b) {
     switch (k) {
-        case 0: return 1;
-        case 1: return a;
-        case 2: return b;
-        case 3: return (long long)a * (a - 1) / 2;
-        case 4: return (long long)a * b;
-        default: return (long long)b * (b - 1) / 2;
+        case 0: return 1u;
+        case 1: return (unsigned)a;
+        case 2: return (unsigned)b;
+        case 3: return (unsigned)(a * (a - 1) / 2);
+        case 4: return (unsigned)(a * b);
+        default: return (unsigned)(b * (b - 1) / 2);
     }
 }
 // index within a kind -> up to two active codes (ascending)
@@ -173,7 +173,7 @@ __device__ bool block_setup(const DevProblem &P, const WalkerCtx &W, int rk, int
     if (b.vp[0] < 0 || b.vp[1] < 0 || b.vp[0] + b.vp[1] > 2) return false;
     b.nra = r0 + r1;
     b.npa = p0 + p1;
-    long long nrk = kind_count(rk, W.e[0], W.e[1]);
+    unsigned nrk = kind_count(rk, W.e[0], W.e[1]);
     b.npk = kind_count(pk, W.h[0], W.h[1]);
     b.ng = nrk * b.npk;
     if (b.ng == 0) return false;
@@ -202,19 +202,19 @@ __device__ bool block_setup(const DevProblem &P, const WalkerCtx &W, int rk, int
 // keys are settled by that one load, so several lookups can have their first
 // loads in flight together; after a collision probing goes on one by one.
 __device__ __forceinline__ uint2 probe_from(const DevTable &t, unsigned long long key, ulonglong2 s,
-                                            unsigned long long slot) {
+                                            unsigned slot) {
     while (true) {
         if (s.x == key) return make_uint2((unsigned)s.y, (unsigned)(s.y >> 32));
         if (s.x == SCQ_EMPTY_KEY) return make_uint2(0u, 0u);
-        slot = (slot + 1) & t.mask;
+        slot = (slot + 1u) & (unsigned)t.mask;
         s = t.slots[slot];
     }
 }
 
 // group g of block b: decode (Ra, Pa), form x_m, do the lookups of its overlap type
-__device__ void group_setup(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, const Block &b, long long g,
+__device__ void group_setup(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, const Block &b, unsigned g,
                             GroupInfo &G, uint2 *lst) {
-    unsigned ri = (unsigned)(g / b.npk), pi = (unsigned)(g - (long long)ri * b.npk);
+    unsigned ri = g / b.npk, pi = g - ri * b.npk;
     int ra0, ra1, pa0, pa1;
     kind_decode(b.rk, ri, L.occ, L.occ + 32, W.e[1], ra0, ra1);
     kind_decode(b.pk, pi, L.hol, L.hol + 32, W.h[1], pa0, pa1);
@@ -242,7 +242,7 @@ __device__ void group_setup(const DevProblem &P, const WalkerCtx &W, const WaveL
     } else {
         // y-list, then the nonempty x-lists of x - r (ascending r; r in the top
         // byte of .y); first probes issued four at a time
-        unsigned long long hy = scq_hash(x) & P.ytab.mask;
+        unsigned hy = (unsigned)scq_hash(x) & (unsigned)P.ytab.mask;
         ulonglong2 sy = P.ytab.slots[hy];
         int k = 1;
         unsigned long long y = x;
@@ -259,8 +259,9 @@ __device__ void group_setup(const DevProblem &P, const WalkerCtx &W, const WaveL
             unsigned long long k1 = r1 >= 0 ? x & ~(1ull << r1) : k0;
             unsigned long long k2 = r2 >= 0 ? x & ~(1ull << r2) : k0;
             unsigned long long k3 = r3 >= 0 ? x & ~(1ull << r3) : k0;
-            unsigned long long h0 = scq_hash(k0) & P.xtab.mask, h1 = scq_hash(k1) & P.xtab.mask;
-            unsigned long long h2 = scq_hash(k2) & P.xtab.mask, h3 = scq_hash(k3) & P.xtab.mask;
+            unsigned xm = (unsigned)P.xtab.mask;
+            unsigned h0 = (unsigned)scq_hash(k0) & xm, h1 = (unsigned)scq_hash(k1) & xm;
+            unsigned h2 = (unsigned)scq_hash(k2) & xm, h3 = (unsigned)scq_hash(k3) & xm;
             ulonglong2 s0 = P.xtab.slots[h0], s1 = P.xtab.slots[h1], s2 = P.xtab.slots[h2], s3 = P.xtab.slots[h3];
             uint2 o = probe_from(P.xtab, k0, s0, h0);
             if (o.y) lst[k++] = make_uint2(o.x, o.y | ((unsigned)r0 << 24));
@@ -821,7 +822,7 @@ struct Acc {
     double best;                      // first-reaction clock of the best group so far
     unsigned long long bestkey;
     int bestblk;                      // rk * 6 + pk
-    long long bestg;
+    int bestg;
 };
 
 // sub-wave sum over S consecutive lanes (S a power of two), fixed tree
@@ -846,8 +847,8 @@ __device__ void sweep_block(const DevProblem &P, const WalkerCtx &W, const WaveL
     int vp = b.vp[0] + b.vp[1];
     RowDec d;
     if (ntile == 1 && sub < b.R) row_decode(P, W, b, sub, d);
-    for (long long gb = 0; gb < b.ng; gb += WAVE) {
-        long long g = gb + lane;
+    for (unsigned gb = 0; gb < b.ng; gb += WAVE) {
+        unsigned g = gb + (unsigned)lane;
         bool live = false;
         if (g < b.ng) {
             group_setup(P, W, L, b, g, mg, mlst);
@@ -915,7 +916,7 @@ __device__ void sweep_block(const DevProblem &P, const WalkerCtx &W, const WaveL
                 a.best = tau;
                 a.bestkey = mg.xkey;
                 a.bestblk = b.rk * 6 + b.pk;
-                a.bestg = g;
+                a.bestg = (int)g;
             }
         }
         __syncwarp();
@@ -964,7 +965,7 @@ __device__ void walker_eval(const DevProblem &P, const WaveLDS &L, int lane, uns
         double ob = __shfl_xor(a.best, d);
         unsigned long long okk = __shfl_xor(a.bestkey, d);
         int obk = __shfl_xor(a.bestblk, d);
-        long long og = __shfl_xor(a.bestg, d);
+        int og = __shfl_xor(a.bestg, d);
         if (ob < a.best || (ob == a.best && okk < a.bestkey)) { a.best = ob; a.bestkey = okk; a.bestblk = obk; a.bestg = og; }
     }
     if (a.bestblk < 0) return;
@@ -972,7 +973,7 @@ __device__ void walker_eval(const DevProblem &P, const WaveLDS &L, int lane, uns
     block_setup(P, W, a.bestblk / 6, a.bestblk % 6, b);
     GroupInfo &sg = L.G[WAVE];
     uint2 *slst = L.lst + WAVE * L.NL;
-    if (lane == 0) group_setup(P, W, L, b, a.bestg, sg, slst);
+    if (lane == 0) group_setup(P, W, L, b, (unsigned)a.bestg, sg, slst);
     __syncwarp();
     GroupView sgv = group_view<true>(L, WAVE);
     int vp = b.vp[0] + b.vp[1];
@@ -1422,8 +1423,8 @@ __global__ __launch_bounds__(64) void k_neighbors(DevProblem P, unsigned long lo
             int vp = b.vp[0] + b.vp[1];
             GroupInfo &mg = L.G[lane];
             uint2 *mlst = L.lst + lane * L.NL;
-            for (long long gb = 0; gb < b.ng; gb += WAVE) {
-                long long g = gb + lane;
+            for (unsigned gb = 0; gb < b.ng; gb += WAVE) {
+                unsigned g = gb + (unsigned)lane;
                 if (g < b.ng) {
                     group_setup(P, W, L, b, g, mg, mlst);
                     for (unsigned r = 0; r < b.R; r++) {
