@@ -78,6 +78,11 @@ def test_batch_autotune_then_sample():
     systems = _systems()[:3]
     engines = [_fresh(prob, W) for prob, W in systems]
     b = Batch(engines)
+    from paper_1909_06935_amd.scqmc import ScqmcError
+    for bad in (lambda: b.set_queue(-1), lambda: b.set_queue(5000), lambda: b.set_schedule(3, 1),
+                lambda: b.set_schedule(0, 0)):
+        with pytest.raises(ScqmcError):
+            bad()
     order, spl, ms = b.tune(4)
     _say("tuned", order, spl, b.bin, ms)
     assert order in (0, 1, 2) and spl in (1, 2, 4) and b.bin in (0, 1, 4) and ms > 0
