@@ -7,7 +7,6 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC_DIR = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libscqmc.so")
-SOURCES = ["scqmc_host.hip", "scqmc_walk.hip", "scqmc_setup.hip", "scqmc_device.h"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -27,13 +26,6 @@ def build(verbose: bool = False) -> str:
     if verbose:
         print(" ".join(cmd))
     return LIB
-
-
-def stale() -> bool:
-    if not os.path.exists(LIB):
-        return True
-    t = os.path.getmtime(LIB)
-    return any(os.path.getmtime(os.path.join(SRC_DIR, s)) > t for s in SOURCES)
 
 
 if __name__ == "__main__":

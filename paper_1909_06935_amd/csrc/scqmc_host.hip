@@ -365,6 +365,10 @@ static scqmc_status build_table(scqmc_ctx *c, int mode, const DBuf &rkeys, long 
     int ne = c->nea + c->neb;
     long long per = mode == 0 ? 1 : mode == 1 ? ne : (long long)ne * (ne - 1) / 2;
     long long M = n * per;
+    // list offsets, counts and entry indices are 32-bit on the device
+    if (M >= (1LL << 32))
+        FAIL(c, SCQMC_E_UNSUPPORTED, "reference expands to " + std::to_string(M) +
+                                         " list entries; the tables hold fewer than 2^32");
     hipStream_t st = c->stream;
     DBuf ekeys, epay, cnt, off, cur, slot_of, tmp, total, scratch, uniq;
     TRY(dalloc(c, ekeys, sizeof(unsigned long long) * M));

@@ -220,16 +220,74 @@ class Brute:
 # closed-form neighbour counts (frozen core, at most two virtual electrons)
 # ---------------------------------------------------------------------------
 
-def eloc_tol(eloc, sabs, kappa, n_nbr, floor=1e-10):
-    """Parity tolerance for a local energy E_L = H_nn + sum_m H_nm psi(m)/psi(n).
+# Parity rule for local energies (the bar every GPU-vs-oracle comparison uses).
+#
+# kappa(n) = A(n) / |psi(n)|, A(n) the sum of the magnitudes of the terms of
+# psi(n) = c_l <n|H|phi0>, is the condition number of the walker's own overlap:
+# every term of E_L - H_nn is divided by psi(n), so E_L carries a relative
+# error of about 2^-53 kappa on that part in any summation order.
+#   * kappa > ZERO_KAPPA: psi(n) is below 1e-12 of its own term sum -- the
+#     terms cancel (e.g. by spin symmetry of the reference) and what is left is
+#     rounding noise.  Such an overlap is numerically zero; its E_L has no
+#     meaningful digits in FP64 and is excluded (counted and printed).
+#   * kappa <= WELL_KAPPA (well-conditioned): |dE_L| <= max(1e-10, min(B, 1e-8))
+#     with B the rounding bound below; the widening above 1e-10 is capped.
+#   * WELL_KAPPA < kappa <= ZERO_KAPPA (ill-conditioned): |dE_L| <= max(1e-10, B),
+#     uncapped; counted and printed.
+# B = 8 * 2^-53 * sqrt(|M(n)| + 1) * (S_abs + |E_L| kappa), S_abs =
+# (|H_nn psi(n)| + sum_m |H_nm| A(m)) / |psi(n)| (the oracle reports S_abs and
+# kappa for every determinant).
+ZERO_KAPPA = 1e12
+WELL_KAPPA = 1e6
+WIDEN_CAP = 1e-8
 
-    1e-10 Eh, widened for near-node walkers to the rounding bound of the sum:
-    8 * 2^-53 * sqrt(|M(n)| + 1) * (S_abs + |E_L| * kappa), where S_abs is
-    (|H_nn psi(n)| + sum_m |H_nm| A(m)) / |psi(n)| with A(m) the sum of the
-    magnitudes of the terms of psi(m), and kappa = A(n)/|psi(n)| is the
-    condition number of psi(n) itself (cancellation inside <n|H|phi0>)."""
-    b = 8.0 * 2.0 ** -53 * np.sqrt(np.asarray(n_nbr) + 1.0) * (np.asarray(sabs) + np.abs(eloc) * np.asarray(kappa))
-    return np.maximum(floor, b)
+
+def rounding_bound(eloc, sabs, kappa, n_nbr):
+    return 8.0 * 2.0 ** -53 * np.sqrt(np.asarray(n_nbr, dtype=float) + 1.0) * (
+        np.asarray(sabs) + np.abs(eloc) * np.asarray(kappa))
+
+
+def eloc_tol(eloc, sabs, kappa, n_nbr, floor=1e-10):
+    """Per-determinant tolerance of the parity rule above (NaN where the
+    overlap is numerically zero and the determinant is excluded)."""
+    kappa = np.asarray(kappa, dtype=float)
+    b = rounding_bound(eloc, sabs, kappa, n_nbr)
+    tol = np.where(kappa <= WELL_KAPPA, np.maximum(floor, np.minimum(b, WIDEN_CAP)), np.maximum(floor, b))
+    return np.where(kappa > ZERO_KAPPA, np.nan, tol)
+
+
+def numerically_zero(psi, kappa):
+    """Overlaps that are exactly zero or below 1e-12 of their own term sum."""
+    return (np.asarray(psi) == 0) | (np.asarray(kappa, dtype=float) > ZERO_KAPPA)
+
+
+def eloc_parity(got, ref, psi, kappa, sabs, n_nbr, label, floor=1e-10, quiet=False):
+    """Apply the parity rule to local energies `got` against the oracle's
+    `ref`.  Asserts every compared determinant is within its tolerance;
+    prints and returns the counts (compared, excluded as numerically zero,
+    ill-conditioned, widened beyond `floor`, above `floor`) and the largest
+    error.  NaN in `ref` (no such energy, e.g. the Dyall energy of an
+    active-space determinant) is skipped."""
+    got, ref = np.asarray(got, dtype=float), np.asarray(ref, dtype=float)
+    kappa = np.asarray(kappa, dtype=float)
+    n_nbr = np.broadcast_to(np.asarray(n_nbr, dtype=float), ref.shape)
+    has = ~np.isnan(ref) & (np.asarray(psi) != 0)
+    zero = has & (kappa > ZERO_KAPPA)
+    cmp = has & ~zero
+    tol = eloc_tol(ref, sabs, kappa, n_nbr, floor)
+    err = np.abs(got - ref)
+    bad = cmp & ~(err <= tol)
+    ill = cmp & (kappa > WELL_KAPPA)
+    st = dict(n=int(cmp.sum()), excluded=int(zero.sum()), ill=int(ill.sum()),
+              widened=int((cmp & (tol > floor)).sum()), above_floor=int((cmp & (err > floor)).sum()),
+              max_err=float(err[cmp].max()) if cmp.any() else 0.0,
+              max_err_well=float(err[cmp & ~ill].max()) if (cmp & ~ill).any() else 0.0)
+    if not quiet:
+        print(f"{label}: compared {st['n']}, excluded (numerically zero psi) {st['excluded']}, "
+              f"ill-conditioned {st['ill']}, widened {st['widened']}, above {floor:g} Eh {st['above_floor']}, "
+              f"max |dE| {st['max_err']:.2e} (well-conditioned {st['max_err_well']:.2e})", flush=True)
+    assert not bad.any(), (label, np.nonzero(bad)[0][:5], err[bad][:5], tol[bad][:5])
+    return st
 
 
 def gamma_rtol(kappa, n_nbr, floor=1e-12):

@@ -1,0 +1,165 @@
+"""The 100-orbital CAS(14,14) workload (10 core / 14 active / 76 virtual,
+34 electrons, 50,000-determinant reference, 65,536 walkers) under parity at
+full size, in the benchmark's launch configuration (one step per launch,
+SC-NEVPT2 mode, FP64).
+
+The walkers are equilibrated by the GPU walk itself (30 steps from the
+reference, after which the class mix is stationary), so the snapshots are
+drawn with the walk's own distribution psi^2:
+  * 1,000 equilibrated walkers (every active-space walker among them, at
+    least 20) evaluated on the GPU and by the oracle, element by element
+    (local energy, Dyall local energy, overlap, rate sum, class) under the
+    parity rule of brute.eloc_parity;
+  * the neighbour set M(n), phases, H_nm and psi(m) of three determinants of
+    every kind (active space; one virtual electron of either spin; two
+    virtual electrons aa, ab, bb) bit-exact against the oracle;
+  * one step of all 65,536 walkers, 64 sampled walkers against the oracle
+    walking each alone (same id, seed and step): the new determinant, its
+    overlap and the step's residence-time sums.
+"""
+import os
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import brute
+import oracle as O
+from helpers import virtual_count
+from paper_1909_06935_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+THREADS = min(16, os.cpu_count() or 1)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def cfg3():
+    from paper_1909_06935_amd.scqmc import Engine
+    prob = wl.make_problem("cfg3")
+    prob.eps_virt = np.linspace(1.0, 3.0, prob.space.n_virt)
+    prob.e0_ref = 0.0
+    W = wl.CONFIGS["cfg3"]["walkers"]
+    assert W == 65536
+    _say("cfg3: equilibrating 65,536 walkers (30 steps)")
+    eng = Engine.from_problem(prob, mode=1, burn_in=0, block_len=1)
+    e0 = eng.reference_energy()
+    prob.e0_ref = e0
+    eng.set_dyall(prob.eps_virt, e0)
+    eng.init_walkers(wl.draw_walkers(prob.ref_dets, prob.ref_coeff, W, prob.seed_walk), prob.seed_walk)
+    eng.sample(30)
+    eq, _ = eng.read_walkers()
+    steps, bad = eng.read_counters()
+    assert steps == 30 and bad == 0
+    orc = O.Oracle.from_problem(prob, mode=1)
+    return prob, eng, orc, eq
+
+
+def _kind(sp, d):
+    va, vb = virtual_count(sp, d)
+    return (va, vb)
+
+
+def _n_nbr(sp, d):
+    C, A = sp.n_core, sp.n_act
+    oa, ob = wl.unpack_det(sp, d)
+    a_occ = [sum(C <= p < C + A for p in oa), sum(C <= p < C + A for p in ob)]
+    return brute.count_neighbors(A, sp.n_virt, a_occ, list(virtual_count(sp, d)))
+
+
+def test_cfg3_equilibrated_snapshot_1k(cfg3):
+    prob, eng, orc, eq = cfg3
+    sp = prob.space
+    kinds = np.array([sum(_kind(sp, d)) for d in eq])
+    rng = np.random.Generator(np.random.PCG64(2025))
+    cas = np.nonzero(kinds == 0)[0]
+    assert len(cas) >= 20, len(cas)
+    cas = rng.choice(cas, size=min(len(cas), 40), replace=False)
+    rest = rng.choice(np.nonzero(kinds != 0)[0], size=1000 - len(cas), replace=False)
+    idx = np.concatenate([cas, rest])
+    dets = eq[idx]
+    _say(f"cfg3 snapshot: {len(cas)} active-space, {np.sum(kinds[rest] == 1)} one-virtual, "
+         f"{np.sum(kinds[rest] == 2)} two-virtual walkers; oracle on {THREADS} threads")
+    from test_gpu_parity import compare_eval
+    g = eng.eval_snapshot(dets)
+    ref = orc.eval(dets, nthreads=THREADS)
+    nn = np.array([_n_nbr(sp, d) for d in dets])
+    st = compare_eval(g, ref, nn, "cfg3 1k equilibrated")
+    # walkers are drawn with probability psi^2: none sits on a numerically zero overlap
+    assert st["excluded"] == 0 and st["n"] == 1000, st
+
+
+def _neighbor_table(nb, W2):
+    keys = np.ascontiguousarray(nb["dets"].reshape(len(nb["dets"]), W2)).view(np.dtype((np.void, 8 * W2))).ravel()
+    o = np.argsort(keys)
+    return keys[o], o
+
+
+def compare_neighbors_fast(g, o, W2, label):
+    """Bit-exact set and phases; H_nm to 1e-12; psi(m) to 1e-12 of the largest."""
+    assert g["count"] == len(o["h"]), (label, g["count"], len(o["h"]))
+    kg, og = _neighbor_table(g, W2)
+    ko, oo = _neighbor_table(o, W2)
+    assert np.array_equal(kg, ko), label
+    assert np.array_equal(g["phase"][og], o["phase"][oo]), label
+    assert np.max(np.abs(g["h"][og] - o["h"][oo])) <= 1e-12, label
+    scale = max(1e-300, np.abs(o["psi"]).max())
+    assert np.max(np.abs(g["psi"][og] - o["psi"][oo])) <= 1e-12 * scale, label
+
+
+def test_cfg3_neighbor_sets_every_kind(cfg3):
+    prob, eng, orc, eq = cfg3
+    sp = prob.space
+    rng = np.random.Generator(np.random.PCG64(7))
+    want = [(0, 0), (1, 0), (0, 1), (2, 0), (1, 1), (0, 2)]
+    kinds = [_kind(sp, d) for d in eq]
+    pick = []
+    for k in want:
+        ids = [i for i, kk in enumerate(kinds) if kk == k]
+        assert len(ids) >= 3, (k, len(ids))
+        pick += [(k, eq[i]) for i in rng.choice(ids, size=3, replace=False)]
+    _say(f"cfg3 neighbour sets: {len(pick)} determinants")
+    with ThreadPoolExecutor(max_workers=THREADS) as ex:
+        onb = list(ex.map(lambda kd: orc.neighbors(kd[1]), pick))
+    W2 = 2 * sp.words
+    for (k, d), o in zip(pick, onb):
+        g = eng.debug_neighbors(d)
+        compare_neighbors_fast(g, o, W2, f"cfg3 kind {k}")
+        assert g["count"] == _n_nbr(sp, d)
+        _say(f"cfg3 kind {k}: {g['count']} neighbours, {int(np.sum(o['psi'] != 0))} with psi != 0, identical")
+
+
+def test_cfg3_bench_launch_sampled_walkers(cfg3):
+    """One step of all 65,536 walkers in the benchmark's launch
+    configuration; 64 sampled walkers against the oracle walking each alone."""
+    from paper_1909_06935_amd.scqmc import Engine
+    prob, _, orc, eq = cfg3
+    W = len(eq)
+    eng = Engine.from_problem(prob, mode=1, burn_in=0, block_len=1)
+    seed = 4242
+    eng.init_walkers(eq, seed)
+    eng.sample(1)
+    gd, gpsi = eng.read_walkers()
+    gws = eng.read_walker_sums()
+    steps, bad = eng.read_counters()
+    assert steps == 1 and bad == 0
+    rng = np.random.Generator(np.random.PCG64(12))
+    idx = np.sort(rng.choice(W, size=64, replace=False))
+    _say(f"cfg3 full launch: oracle walks 64 sampled walkers alone on {THREADS} threads")
+
+    def alone(i):
+        return orc.run(eq[i:i + 1], seed, 1, step0=0, burn_in=0, wid0=int(i), nthreads=1)
+
+    with ThreadPoolExecutor(max_workers=THREADS) as ex:
+        res = list(ex.map(alone, idx))
+    for i, (od, opsi, ows, _, stuck) in zip(idx, res):
+        assert stuck == 0
+        assert np.array_equal(gd[i], od[0]), i
+        assert abs(gpsi[i] - opsi[0]) <= 1e-11 * abs(opsi[0]), (i, gpsi[i], opsi[0])
+        assert np.allclose(gws[i], ows[0], rtol=1e-10, atol=1e-12), (i, gws[i], ows[0])

@@ -70,8 +70,6 @@ def test_semicanonicalize(name, prob):
     ok = ref["psi"] != 0
     scale = np.abs(ref["psi"]).max()
     assert np.all(np.abs(got["psi"] - ref["psi"]) <= 1e-11 * scale)
-    tol = brute.eloc_tol(ref["eloc"], ref["sabs"], ref["kappa"], nn, floor=1e-10)
-    assert np.all(np.abs(got["eloc"] - ref["eloc"])[ok] <= tol[ok])
-    okd = ok & ~np.isnan(ref["eloc_d"])
-    told = brute.eloc_tol(ref["eloc_d"], ref["sabs"], ref["kappa"], nn, floor=1e-10)
-    assert np.all(np.abs(got["eloc_d"] - ref["eloc_d"])[okd] <= told[okd])
+    brute.eloc_parity(got["eloc"], ref["eloc"], ref["psi"], ref["kappa"], ref["sabs"], nn, f"{name} rotated E_L")
+    brute.eloc_parity(got["eloc_d"], ref["eloc_d"], ref["psi"], ref["kappa"], ref["sabs"], nn,
+                      f"{name} rotated E_D,L")

@@ -111,7 +111,7 @@ def test_deterministic_repeat():
 
 
 def test_error_paths():
-    from paper_1909_06935_amd.scqmc import Engine, ScqmcError, E_INVALID_ARG, E_STATE
+    from paper_1909_06935_amd.scqmc import Engine, ScqmcError, E_INVALID_ARG, E_NUMERIC, E_STATE
     prob = tiny_problem(TINY[0])
     sp = prob.space
 
@@ -125,7 +125,22 @@ def test_error_paths():
     assert status_of(lambda: e.set_reference(prob.ref_dets, prob.ref_coeff)) == E_STATE
     assert status_of(lambda: e.sample(1)) == E_STATE
     e.set_space(sp)
+    # non-finite integrals
+    h_nan = prob.h1.copy()
+    h_nan[1, 2] = h_nan[2, 1] = np.nan
+    assert status_of(lambda: e.set_integrals_chol(h_nan, prob.chol, prob.e_const)) == E_NUMERIC
+    c_inf = prob.chol.copy()
+    c_inf[0, 0, 0] = np.inf
+    assert status_of(lambda: e.set_integrals_chol(prob.h1, c_inf, prob.e_const)) == E_NUMERIC
+    assert status_of(lambda: e.set_integrals_chol(prob.h1, prob.chol, np.nan)) == E_NUMERIC
     e.set_integrals_chol(prob.h1, prob.chol, prob.e_const)
+    # a reference determinant with the wrong spin projection (one alpha
+    # electron more, one beta electron less)
+    sz = prob.ref_dets.copy()
+    oa, ob = wl.unpack_det(sp, sz[0])
+    free_a = [p for p in range(sp.n_core, sp.n_core + sp.n_act) if p not in oa]
+    sz[0] = wl.pack_det(sp, sorted(list(oa) + free_a[:1]), list(ob)[:-1])
+    assert status_of(lambda: e.set_reference(sz, prob.ref_coeff)) == E_INVALID_ARG
     # a reference determinant with a virtual electron
     bad = prob.ref_dets.copy()
     oa, ob = wl.unpack_det(sp, bad[0])
@@ -149,6 +164,12 @@ def test_error_paths():
     w[0] = wl.pack_det(sp, sorted([p for p in oa if p != 0] + free[:1]), ob)
     assert status_of(lambda: e.init_walkers(w, 1)) == E_INVALID_ARG
     assert status_of(lambda: e.init_walkers(prob.ref_dets[:0], 1)) == E_INVALID_ARG
+    # a walker with psi = 0: an active-space determinant outside the reference
+    cas = wl.cas_dets(sp)
+    ref_keys = {tuple(d.reshape(-1)) for d in prob.ref_dets}
+    absent = [d for d in cas if tuple(d.reshape(-1)) not in ref_keys]
+    assert absent, "the reference of this system leaves some active-space determinants out"
+    assert status_of(lambda: e.init_walkers(np.array(absent[:1]), 1)) == E_INVALID_ARG
     e.init_walkers(prob.ref_dets[:4], 1)
     e.sample(2)
     # a checkpoint of another problem is refused
@@ -185,3 +206,39 @@ def test_sc_coefficient_optimisation_cfg1():
     assert e_final - esc <= 0.01 * (b0.e_var - esc), (e_final, esc, b0.e_var)
     # the sampled energies of the last iterations scatter around the exact value
     assert abs(e_tr[-50:].mean() - e_final) < 0.05 * (b0.e_var - esc)
+
+
+def test_error_bar_calibration_50_seeds_cfg1():
+    """Calibration of the reported jackknife errors (the 50 independent runs
+    of the diatomic-molecule section, used there to measure the spread of
+    SC-NEVPT2(s)): 50 walks of the 12-orbital system with different seeds,
+    each 256 walkers x (100 + 1,000) steps.  The spread of the 50 estimates
+    of E_var, a0^2 and E^(2) must match the errors each run reports:
+    sum_i ((x_i - mean) / sigma_i)^2 / 49 inside the two-sided 99.9 % range
+    of chi^2_49 / 49, [0.52, 1.75]; and the mean of the 50 runs must agree
+    with the exact (brute-force) value within 4 standard errors of that mean."""
+    prob = cfg1_problem()
+    _say("cfg1 error-bar calibration, 50 seeds")
+    b = brute.Brute(prob, wl.dense_eri(prob.chol), eps_virt=prob.eps_virt)
+    w0 = wl.draw_walkers(prob.ref_dets, prob.ref_coeff, 256, prob.seed_walk)
+    keys = (("e_var", "e_var_err", b.e_var), ("a0_sq", "a0_sq_err", b.a0_sq), ("e2", "e2_err", b.e2))
+    vals = {k: [] for k, _, _ in keys}
+    errs = {k: [] for k, _, _ in keys}
+    eng = _engine(prob, mode=1, burn_in=100, block_len=100)
+    for s in range(50):
+        eng.init_walkers(w0, 90001 + 7919 * s)
+        eng.sample(1100)
+        est = eng.read_estimates()
+        for k, ke, _ in keys:
+            vals[k].append(est[k])
+            errs[k].append(est[ke])
+    for k, _, exact in keys:
+        x, sg = np.array(vals[k]), np.array(errs[k])
+        assert np.all(sg > 0), k
+        chi = float(np.sum(((x - x.mean()) / sg) ** 2) / 49.0)
+        sem = float(x.std(ddof=1) / np.sqrt(50))
+        _say(f"{k}: mean {x.mean():.6f} exact {exact:.6f} (diff {abs(x.mean() - exact) / sem:.2f} standard errors); "
+             f"spread of the runs {x.std(ddof=1):.2e} vs reported error rms {np.sqrt(np.mean(sg ** 2)):.2e}; "
+             f"chi^2/49 = {chi:.2f}")
+        assert 0.52 <= chi <= 1.75, (k, chi)
+        assert abs(x.mean() - exact) <= 4.0 * sem, (k, x.mean(), exact, sem)

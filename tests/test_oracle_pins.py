@@ -145,12 +145,13 @@ def test_cfg1_vs_brute(cfg1):
     ok = b.psi != 0
     assert np.max(np.abs(ev["psi"] - b.psi)) < 1e-13
     nnb = b.conn.sum(axis=1)
-    tol = brute.eloc_tol(ev["eloc"], ev["sabs"], ev["kappa"], nnb)
-    assert np.all(np.abs(ev["eloc"][ok] - b.eloc[ok]) < tol[ok])
+    st = brute.eloc_parity(ev["eloc"], np.where(ok, b.eloc, np.nan), b.psi, ev["kappa"], ev["sabs"], nnb,
+                           "cfg1 oracle vs brute E_L")
+    assert st["excluded"] == 0 and st["n"] == ok.sum()
     assert np.max(np.abs(ev["gamma"][ok] - b.gamma[ok]) / b.gamma[ok]) < 1e-12
     okd = ok & (b.cls != 0)
-    told = brute.eloc_tol(ev["eloc_d"], ev["sabs"], ev["kappa"], nnb)
-    assert np.all(np.abs(ev["eloc_d"][okd] - b.eloc_d[okd]) < told[okd])
+    brute.eloc_parity(ev["eloc_d"], np.where(okd, b.eloc_d, np.nan), b.psi, ev["kappa"], ev["sabs"], nnb,
+                      "cfg1 oracle vs brute E_D,L")
 
 
 def test_zero_variance_exact_eigenvector():
