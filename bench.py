@@ -2,25 +2,31 @@
 
 One benchmark "step" is one continuous-time step of every walker: the local
 energy (and Dyall local energy) over the whole neighbour set, the rates, the
-estimator accumulation and the move -- every row of the hot path.  Inputs are
-the seeded synthetic 40-orbital workload (4 core / 8 active / 28 virtual,
-16 electrons, exact CAS(8,8) ground state truncated at |c| > 1e-4), resident
-in HBM before timing starts.
+estimator accumulation and the move -- every row of the hot path.  Default
+workload: the seeded synthetic 100-orbital CAS(14,14) system (10 core / 14
+active / 76 virtual orbitals, 34 electrons, Cholesky rank 200, 50,000-
+determinant selected-CI reference), 65,536 walkers, SC-NEVPT2 mode, FP64,
+all inputs resident in HBM before timing starts.  The walkers start on the
+reference (the costliest class) and first take a fixed burn-in
+(`--burn-in`, 30 steps by default, reported apart) until the class mix is
+stationary; then `--warmup` untimed and `--steps` timed steps.
 
 Prints one JSON line (rank 0, N = 1).  Besides the throughput it carries
   roofline     -- algorithmic bytes per launch of the walker kernel (distinct
                   integrals, one-body entries and reference entries each
                   walker-step reads, counted by the oracle on a sample of the
-                  equilibrated walkers, plus walker state) over the launch
+                  equilibrated walkers, plus walker state) over the mean launch
                   time measured with HIP events on the kernel's stream;
                   `traffic` is the measured HBM bytes per launch (rocprofv3
                   FETCH_SIZE + WRITE_SIZE, copy-calibrated) from the committed
                   counter summary, reported only while the kernel sources are
                   the ones it was taken on; `fp64` the same launch time
                   against the FP64 vector peak with a minimal flop count;
-  cpu_baseline -- the CPU oracle on a bounded sample of the same walkers.
+                  `bound` names the largest of the measured fractions;
+  cpu_baseline -- the CPU oracle on a bounded sample of the same walkers
+                  (median of five timed repeats).
 
-usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config cfg2|cfg3]
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--burn-in B] [--config cfg3|cfg2|batch|serve]
 """
 import argparse
 import json
@@ -39,6 +45,8 @@ FP64_PEAK_TFLOPS = 78.6
 # wave64 instruction per SIMD every 4 cycles (16 lanes per cycle)
 VALU_PEAK_WAVE_INSTR = 256 * 4 * 2.4e9 / 4
 WALKER_STATE_BYTES = 2 * (8 + 4 + 8 + 24)   # key, virtual codes, psi, per-walker sums; read + write
+
+BURN_IN = {"cfg2": 300, "cfg3": 30}
 
 WORKLOADS = {
     "cfg2": "40 orbitals (4 core / 8 active / 28 virtual), 16 electrons, Sz=0, Cholesky rank 80; "
@@ -59,11 +67,13 @@ def make_problem(name):
     return prob
 
 
-def cpu_baseline(prob, dets, seed, step, budget_s=20.0, threads=None):
+def cpu_baseline(prob, dets, seed, step, budget_s=20.0, threads=None, repeats=5):
     """Oracle (as it stands) on a bounded sample of the equilibrated walkers:
-    one continuous-time step each, all host threads."""
+    one continuous-time step each, all host threads; the sample is sized so
+    that `repeats` timed runs take about budget_s together, and the median
+    rate is reported."""
     import oracle as O
-    threads = threads or os.cpu_count()
+    threads = threads or min(16, os.cpu_count() or 1)
     orc = O.Oracle.from_problem(prob, mode=1)
     rng = np.random.Generator(np.random.PCG64(99))
     # calibrate on a small sample, then size the timed sample to the budget
@@ -72,13 +82,17 @@ def cpu_baseline(prob, dets, seed, step, budget_s=20.0, threads=None):
     t = time.perf_counter()
     orc.run(dets[idx], seed, 1, step0=step, burn_in=0, wid0=0, nthreads=threads)
     dt = time.perf_counter() - t
-    n = int(min(len(dets), max(n0, budget_s / max(dt / n0, 1e-6))))
+    n = int(min(len(dets), max(n0, budget_s / repeats / max(dt / n0, 1e-6))))
     idx = rng.choice(len(dets), size=n, replace=False)
-    t = time.perf_counter()
-    orc.run(dets[idx], seed, 1, step0=step, burn_in=0, wid0=0, nthreads=threads)
-    dt = time.perf_counter() - t
-    return orc, idx, dict(value=n / dt, unit="walker-steps/s", cores=threads, kind="oracle",
-                          sample=f"{n} equilibrated walkers x 1 step, {dt:.1f} s on {threads} threads")
+    rates = []
+    for _ in range(repeats):
+        t = time.perf_counter()
+        orc.run(dets[idx], seed, 1, step0=step, burn_in=0, wid0=0, nthreads=threads)
+        rates.append(n / (time.perf_counter() - t))
+    med = float(np.median(rates))
+    return orc, idx, dict(value=med, unit="walker-steps/s", cores=threads, kind="oracle",
+                          sample=f"{n} equilibrated walkers x 1 step, median of {repeats} repeats "
+                                 f"({n / med:.1f} s each) on {threads} threads")
 
 
 def algorithmic_work(orc, dets, nmax=256):
@@ -88,7 +102,7 @@ def algorithmic_work(orc, dets, nmax=256):
     neighbour."""
     from concurrent.futures import ThreadPoolExecutor
     sel = dets[:nmax]
-    with ThreadPoolExecutor(max_workers=os.cpu_count()) as ex:
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
         tr = list(ex.map(orc.traffic, sel))
     per = [8 * x["eri"] + 8 * x["heff"] + 16 * x["ref"] + WALKER_STATE_BYTES for x in tr]
     flops = [2 * x["terms"] + 3 * x["n_nbr"] for x in tr]
@@ -151,9 +165,12 @@ def measured_valu(config, walker_steps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=300)
-    ap.add_argument("--config", default="cfg2", choices=["cfg2", "cfg3", "batch", "serve"])
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--burn-in", type=int, default=None,
+                    help="steps walked from the reference before the warm-up (default 30 at 100 orbitals, "
+                         "300 at 40); the batched and serving forms ignore it")
+    ap.add_argument("--config", default="cfg3", choices=["cfg2", "cfg3", "batch", "serve"])
     ap.add_argument("--requests", type=int, default=100, help="serve: number of requests")
     ap.add_argument("--rate", type=float, default=4.0, help="serve: arrivals per second")
     ap.add_argument("--target-err", type=float, default=1e-2, help="serve: target E_var error (Eh)")
@@ -199,16 +216,27 @@ def main():
 
     prob = make_problem(args.config)
     W = args.walkers or wl.CONFIGS[args.config]["walkers"]
+    burn = BURN_IN[args.config] if args.burn_in is None else args.burn_in
     stream = torch.cuda.Stream()
-    eng = Engine.from_problem(prob, mode=1, burn_in=args.warmup, block_len=args.block, stream=stream)
+    acc_from = burn + args.warmup    # estimators accumulate over the timed steps only
+    eng = Engine.from_problem(prob, mode=1, burn_in=acc_from, block_len=args.block, stream=stream)
     if args.precision == "fp32":
-        eng.set_options(mode=1, precision=1, burn_in=args.warmup, block_len=args.block)
+        eng.set_options(mode=1, precision=1, burn_in=acc_from, block_len=args.block)
     if prob.e0_ref == 0.0:
         # no stored CAS energy for this workload: E_0^(0) of its reference, on the device
         eng.set_dyall(prob.eps_virt, eng.reference_energy())
     w0 = wl.draw_walkers(prob.ref_dets, prob.ref_coeff, W, prob.seed_walk)
     eng.init_walkers(w0, prob.seed_walk)
-    print(f"# {args.config}: {W} walkers, warmup {args.warmup} steps", file=sys.stderr, flush=True)
+    print(f"# {args.config}: {W} walkers, burn-in {burn} steps, warm-up {args.warmup}, timed {args.steps}",
+          file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for k in range(burn):
+        eng.sample(1)
+        if k % 10 == 9 or k == burn - 1:
+            eng.synchronize()
+            print(f"# burn-in {k + 1}/{burn}: {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    eng.synchronize()
+    burn_s = time.perf_counter() - t0
     eng.sample(args.warmup)
     eng.synchronize()
 
@@ -238,6 +266,8 @@ def main():
         "n_gpus": 1,
         "steps": K,
         "warmup": args.warmup,
+        "burn_in": {"steps": burn, "seconds": burn_s,
+                    "note": "walked from the reference before the warm-up; not timed"},
         "ms_per_step": 1e3 * wall / K,
         "higher_is_better": True,
         "scaling": "weak",
@@ -257,25 +287,34 @@ def main():
         avg_s = float(np.mean(launch_ms)) * 1e-3
         ach = per_launch / avg_s / 1e9
         fl = per_flops * W * args.block / avg_s / 1e12
+        tr = measured_traffic(args.config, W * args.block)
+        vi = measured_valu(args.config, W * args.block)
+        # the three fractions: algorithmic bytes, measured fabric bytes and
+        # VALU issue (the last two from the committed counter summaries, only
+        # while the kernel sources are the ones they were taken on)
+        fracs = {"hbm_algorithmic": ach / HBM_PEAK_GBS}
+        if tr is not None:
+            fracs["hbm_measured"] = tr / avg_s / (HBM_PEAK_GBS * 1e9)
+        if vi is not None:
+            fracs["valu_issue"] = vi[0] / avg_s / VALU_PEAK_WAVE_INSTR
+        binding = max(fracs, key=fracs.get)
+        if binding == "valu_issue":
+            va = vi[0] / avg_s
+            head = {"bound": "alu", "achieved": va, "peak": VALU_PEAK_WAVE_INSTR, "unit": "wave64 VALU instr/s",
+                    "frac": va / VALU_PEAK_WAVE_INSTR}
+        else:
+            head = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": ach / HBM_PEAK_GBS}
         out["roofline"] = {
-            "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-            "traffic": measured_traffic(args.config, W * args.block), "kernel": "k_sample",
-            "avg_launch_ms": avg_s * 1e3,
+            **head, "traffic": tr, "kernel": "k_sample", "binding_fraction": binding, "fractions": fracs,
+            "algorithmic_gbs": ach, "avg_launch_ms": avg_s * 1e3,
             "bytes_per_walker_step": per_bytes, "walker_steps_per_launch": W * args.block,
             "count_sample": nsamp,
             "fp64": {"achieved": fl, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": fl / FP64_PEAK_TFLOPS,
                      "flops_per_walker_step": per_flops},
         }
-        tr = out["roofline"]["traffic"]
-        if tr is not None:
-            # measured fabric bytes over the same launch time: the third fraction
-            out["roofline"]["traffic_frac"] = tr / avg_s / (HBM_PEAK_GBS * 1e9)
-        vi = measured_valu(args.config, W * args.block)
         if vi is not None:
-            va = vi[0] / avg_s
-            out["roofline"]["valu"] = {"achieved": va, "peak": VALU_PEAK_WAVE_INSTR, "unit": "wave64 instr/s",
-                                       "frac": va / VALU_PEAK_WAVE_INSTR,
-                                       "salu_frac": vi[1] / avg_s / (256 * 2.4e9)}
+            out["roofline"]["salu_frac"] = vi[1] / avg_s / (256 * 2.4e9)
         out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 

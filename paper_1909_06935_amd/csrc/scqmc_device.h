@@ -198,6 +198,26 @@ template <class R = double>
 __device__ __forceinline__ R double_elem(const DevProblem &P, int P1, int P2, int Q1, int Q2) {
     return seri<R>(P, Q1, P1, Q2, P2) - seri<R>(P, Q1, P2, Q2, P1);
 }
+// The same with a lane-varying added spin-orbital X (X = Q1 or Q2; the virtual
+// that differs between the rows a wave evaluates side by side), Y the other
+// added one: with PX / PY the removed partners of X / Y in the first term,
+//   (Q1 P1|Q2 P2) = (Y PY|X PX) at [Y][PY][PX][X],
+//   (Q1 P2|Q2 P1) = (Y PX|X PY) at [Y][PX][PY][X],
+// so X is the last index of both reads and the lanes of a load share lines
+// whatever the order of X and the other indices.
+template <class R = double>
+__device__ __forceinline__ R double_elem_x(const DevProblem &P, int P1, int P2, int Q1, int Q2, bool x_is_q2) {
+    int X = x_is_q2 ? Q2 : Q1, Y = x_is_q2 ? Q1 : Q2;
+    int PX = x_is_q2 ? P2 : P1, PY = x_is_q2 ? P1 : P2;
+    int sx = g_spin(P, X), sy = g_spin(P, Y), spx = g_spin(P, PX), spy = g_spin(P, PY);
+    unsigned Np = (unsigned)P.Np;
+    unsigned x = (unsigned)g_idx(P, X), y = (unsigned)g_idx(P, Y), px = (unsigned)g_idx(P, PX),
+             py = (unsigned)g_idx(P, PY);
+    const R *E = Ints<R>::eri(P);
+    R a = (sy == spy && sx == spx) ? E[((y * Np + py) * Np + px) * Np + x] : R(0);
+    R b = (sy == spx && sx == spy) ? E[((y * Np + px) * Np + py) * Np + x] : R(0);
+    return a - b;
+}
 
 // one-body part of a single P -> Q from determinant b:
 // h_eff[Q][P] + sum_{J in b, J != P} [(QP|JJ) - (QJ|JP)]; with_virt = 0 drops

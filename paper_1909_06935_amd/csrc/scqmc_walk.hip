@@ -299,15 +299,18 @@ __device__ __forceinline__ double wphase_double(const WaveLDS &L, int P1, int P2
 // electron in the sum; *act receives the sum over active electrons only
 // (Dyall's H_0)
 // Coulomb and exchange integrals of electron j with the pair (p, q), lo/hi
-// = min/max(p, q):  (jj|pq) at j (Np^3 + Np^2) + lo Np + hi and
-// (pj|jq) = (lo j|j hi) at lo Np^3 + hi + j (Np^2 + Np): two multiply-adds
-// per electron, the largest (virtual) index last.
+// = min/max(p, q), or hi = the lane-varying one:  (jj|pq) at
+// j (Np^3 + Np^2) + lo Np + hi and (pj|jq) = (lo j|j hi) at
+// lo Np^3 + hi + j (Np^2 + Np): two multiply-adds per electron, the varying
+// (or else the largest) index last.
 struct JKOff {
     unsigned offJ, offK, cJ, cK;
 };
-__device__ __forceinline__ JKOff jk_offsets(const DevProblem &P, int p, int q) {
+// v: the lane-varying orbital if it is p or q (it becomes `hi`, the last index)
+__device__ __forceinline__ JKOff jk_offsets(const DevProblem &P, int p, int q, int v = -1) {
     unsigned Np = (unsigned)P.Np, N2 = Np * Np, N3 = N2 * Np;
     unsigned lo = (unsigned)min(p, q), hi = (unsigned)max(p, q);
+    if (v >= 0 && (v == p || v == q)) { hi = (unsigned)v; lo = (unsigned)(p + q - v); }
     JKOff o;
     o.offJ = lo * Np + hi;
     o.offK = lo * N3 + hi;
@@ -325,9 +328,9 @@ __device__ __forceinline__ R jk_term(const DevProblem &P, const JKOff &o, int j,
 
 template <class R>
 __device__ __forceinline__ double single_elem_w2(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, int gP,
-                                                 int gQ, double *act) {
+                                                 int gQ, int vq, double *act) {
     int p = g_idx(P, gP), q = g_idx(P, gQ), sp = g_spin(P, gP);
-    JKOff o = jk_offsets(P, p, q);
+    JKOff o = jk_offsets(P, p, q, vq);
     double v = (double)Ints<R>::heff(P)[q * P.Np + p];
 #pragma unroll 4
     for (int i = 0; i < W.ne; i++) {
@@ -469,14 +472,18 @@ __device__ double phi1(const DevProblem &P, unsigned long long y, int s, int sg,
 }
 
 // <m|H|phi0> for m = x + virtuals s1 < s2, from the x-list of x (signed coefficients)
-// (a1 t|a2 u) is read as (t a1|u a2): the row's virtual orbitals a1, a2 give
-// a lane offset a1*Np^2 + a2, the entry's active orbitals t*Np^3 + u*Np.
+// (a1 t|a2 u) is read as (t a1|u a2) at [t][a1][u][a2] (lane offset
+// a1*Np^2 + a2, entry offset t*Np^3 + u*Np), or, when a1 is the virtual
+// orbital that changes from lane to lane (vq), as (u a2|t a1) at
+// [u][a2][t][a1]: either way the lane-varying index is the last one.
 template <bool U, class R>
-__device__ __forceinline__ double phi2(const DevProblem &P, int s1, int s2, uint2 ox) {
+__device__ __forceinline__ double phi2(const DevProblem &P, int s1, int s2, uint2 ox, int vq) {
     int sg1 = s1 >= P.V, sg2 = s2 >= P.V;
     unsigned Np = (unsigned)P.Np, N3 = Np * Np * Np;
     unsigned a1 = (unsigned)(P.A + s1 - sg1 * P.V), a2 = (unsigned)(P.A + s2 - sg2 * P.V);
-    const R *E = Ints<R>::eri(P) + (a1 * Np) * Np + a2;
+    bool sw = vq == (int)a1;
+    const R *E = Ints<R>::eri(P) + (sw ? (a2 * Np) * Np + a1 : (a1 * Np) * Np + a2);
+    unsigned Ct = sw ? Np : N3, Cu = sw ? N3 : Np;   // entry offset t*Ct + u*Cu of (t a1|u a2)
     double acc = 0.0;
     // wave-uniform group: four entries' integrals in flight at a time (same
     // order of additions)
@@ -494,14 +501,14 @@ __device__ __forceinline__ double phi2(const DevProblem &P, int s1, int s2, uint
                 w[j] = tload<U>(P.xtab.vals, ox.x + k + j);
             }
 #pragma unroll
-            for (int j = 0; j < PU; j++) e[j] = E[((c[j] >> 6) & 31u) * N3 + (c[j] & 31u) * Np];
+            for (int j = 0; j < PU; j++) e[j] = E[((c[j] >> 6) & 31u) * Ct + (c[j] & 31u) * Cu];
 #pragma unroll
             for (int j = 0; j < PU; j++) acc += w[j] * (double)e[j];
         }
         for (; k < ox.y; k++) {
             unsigned code = tload<U>(P.xtab.codes, ox.x + k);
             unsigned t = (code >> 6) & 31u, u = code & 31u;
-            acc += tload<U>(P.xtab.vals, ox.x + k) * (double)E[t * N3 + u * Np];
+            acc += tload<U>(P.xtab.vals, ox.x + k) * (double)E[t * Ct + u * Cu];
         }
         return ((P.neb + 1) & 1) ? -acc : acc;
     }
@@ -517,8 +524,8 @@ __device__ __forceinline__ double phi2(const DevProblem &P, int s1, int s2, uint
 #pragma unroll
         for (int j = 0; j < PU; j++) {
             unsigned t = (c[j] >> 6) & 31u, u = c[j] & 31u;
-            e1[j] = E[t * N3 + u * Np];
-            e2[j] = E[u * N3 + t * Np];
+            e1[j] = E[t * Ct + u * Cu];
+            e2[j] = E[u * Ct + t * Cu];
         }
 #pragma unroll
         for (int j = 0; j < PU; j++) acc += w[j] * (double)(e1[j] - e2[j]);
@@ -526,7 +533,7 @@ __device__ __forceinline__ double phi2(const DevProblem &P, int s1, int s2, uint
     for (; k < ox.y; k++) {
         unsigned code = tload<U>(P.xtab.codes, ox.x + k);
         unsigned t = (code >> 6) & 31u, u = code & 31u;
-        acc += tload<U>(P.xtab.vals, ox.x + k) * (double)(E[t * N3 + u * Np] - E[u * N3 + t * Np]);
+        acc += tload<U>(P.xtab.vals, ox.x + k) * (double)(E[t * Ct + u * Cu] - E[u * Ct + t * Cu]);
     }
     return acc;
 }
@@ -560,7 +567,8 @@ __device__ double psi_direct(const DevProblem &P, unsigned long long key, unsign
             });
         return P.ccls[class_id1(P.V, vcode[0])] * phi;
     }
-    return P.ccls[class_id2(P.V, vcode[0], vcode[1])] * phi2<false, R>(P, vcode[0], vcode[1], table_find(P.xtab, key));
+    return P.ccls[class_id2(P.V, vcode[0], vcode[1])] *
+           phi2<false, R>(P, vcode[0], vcode[1], table_find(P.xtab, key), -1);
 }
 
 // Row r of a block, independent of the group: the virtual set of m, its
@@ -571,6 +579,8 @@ struct RowDec {
     int ad0, ad1;        // added virtual electrons (g codes, -1 absent)
     double c;            // SC coefficient of m's class
     int cls;
+    int vq;              // orbital index (0..Np-1) of the added virtual electron that changes fastest
+                         // from row to row (consecutive lanes), -1 if none is added
     bool same;           // m keeps the walker's virtual set
 };
 
@@ -612,6 +622,10 @@ __device__ __forceinline__ void row_decode(const DevProblem &P, const WalkerCtx 
     }
     d.ad0 = x0 >= 0 ? g_of_virtual(P, x0) : -1;
     d.ad1 = x1 >= 0 ? g_of_virtual(P, x1) : -1;
+    // r = i0 * c1 + i1: the beta part (i1) changes fastest; inside a pair the
+    // smaller index i does; so it is x0 except for an alpha-beta pair (x1)
+    int xf = (a0 == 1 && a1 == 1) ? x1 : x0;
+    d.vq = xf >= 0 ? g_idx(P, g_of_virtual(P, xf)) : -1;
     int vp = b.vp[0] + b.vp[1];
     if (vp == 0) {
         d.Lp0 = d.Lp1 = -1;
@@ -696,12 +710,15 @@ __device__ __forceinline__ void row_eval(const DevProblem &P, const WalkerCtx &W
         double ph = wphase_single(L, Pr0, Qa0);
         double act;
         o.phase = ph;
-        o.hnm = ph * single_elem_w2<R>(P, W, L, Pr0, Qa0, &act);
+        o.hnm = ph * single_elem_w2<R>(P, W, L, Pr0, Qa0, d.vq, &act);
         o.hd = ph * act;
     } else {
         double ph = wphase_double(L, Pr0, Pr1, Qa0, Qa1);
         o.phase = ph;
-        o.hnm = ph * (double)double_elem<R>(P, Pr0, Pr1, Qa0, Qa1);
+        // the lane-varying virtual, when the row adds one, is read as the last index
+        double e = (d.vq >= 0) ? (double)double_elem_x<R>(P, Pr0, Pr1, Qa0, Qa1, g_idx(P, Qa1) == d.vq)
+                               : (double)double_elem<R>(P, Pr0, Pr1, Qa0, Qa1);
+        o.hnm = ph * e;
         o.hd = o.hnm;
         if (P.eps_screen > 0.0 && !(fabs(o.hnm) > P.eps_screen)) { o.ok = false; o.psi = 0.0; return; }
     }
@@ -715,7 +732,7 @@ __device__ __forceinline__ void row_eval(const DevProblem &P, const WalkerCtx &W
                          [&](int k) -> uint2 { return view_list<U>(G, k); },
                          [&](int gT, int gS) -> double { return fock_y<R>(P, W, L, G.rg0, G.rg1, G.pg0, G.pg1, gT, gS); });
     } else {
-        phi = phi2<U, R>(P, d.Lp0, d.Lp1, view_list<U>(G, 0));
+        phi = phi2<U, R>(P, d.Lp0, d.Lp1, view_list<U>(G, 0), d.vq);
     }
     o.psi = d.c * phi;
 }

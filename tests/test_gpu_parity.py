@@ -267,3 +267,36 @@ def test_cfg2_bench_launch_sampled_walkers(precision):
         moved_same += same
     if precision:
         assert moved_same >= 90 and close >= 85, (moved_same, close)
+
+
+def test_cfg2_equilibrated_snapshot_1k():
+    """1,000 walkers of the 40-orbital workload drawn by the GPU walk itself
+    (16,384 walkers, 40 steps from the reference), element by element against
+    the oracle; every active-space walker of the set is included."""
+    prob = wl.make_problem("cfg2")
+    prob.eps_virt = np.linspace(1.0, 3.0, prob.space.n_virt)
+    prob.e0_ref = float(np.load(wl.reference_file("cfg2"))["e_cas"])
+    _say("cfg2 equilibrated snapshot")
+    W = wl.CONFIGS["cfg2"]["walkers"]
+    eng = engine_for(prob, mode=1, burn_in=0, block_len=1)
+    eng.init_walkers(wl.draw_walkers(prob.ref_dets, prob.ref_coeff, W, prob.seed_walk), prob.seed_walk)
+    eng.sample(40)
+    eq, _ = eng.read_walkers()
+    from helpers import virtual_count
+    kinds = np.array([sum(virtual_count(prob.space, d)) for d in eq])
+    rng = np.random.Generator(np.random.PCG64(404))
+    cas = np.nonzero(kinds == 0)[0]
+    cas = rng.choice(cas, size=min(len(cas), 100), replace=False)
+    rest = rng.choice(np.nonzero(kinds != 0)[0], size=1000 - len(cas), replace=False)
+    dets = eq[np.concatenate([cas, rest])]
+    orc = O.Oracle.from_problem(prob, mode=1)
+    ref = orc.eval(dets, nthreads=16)
+    sp = prob.space
+    nn = []
+    for d in dets:
+        oa, ob = wl.unpack_det(sp, d)
+        lim = sp.n_core + sp.n_act
+        a_occ = [sum(sp.n_core <= p < lim for p in oa), sum(sp.n_core <= p < lim for p in ob)]
+        nn.append(brute.count_neighbors(sp.n_act, sp.n_virt, a_occ, list(virtual_count(sp, d))))
+    st = compare_eval(eng.eval_snapshot(dets), ref, np.array(nn), "cfg2 1k equilibrated")
+    assert st["excluded"] == 0 and st["n"] == 1000, st
