@@ -14,6 +14,7 @@
 #include <string>
 #include <vector>
 #include <chrono>
+#include <mutex>
 
 #include "../../include/scqmc.h"
 #include "scqmc_setup.hip"
@@ -57,6 +58,7 @@ struct scqmc_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    void *scratch_ptr = nullptr;   // device address of this device's allocation-free scratch array
     std::string err;
     bool has_space = false, has_ints = false, has_ref = false, has_coef = false, has_dyall = false,
          has_walkers = false;
@@ -202,6 +204,36 @@ static bool all_finite(const double *x, size_t n) {
 
 extern "C" {
 
+// ---------------------------------------------------------------------------
+// Fixed device memory of the allocation-free snapshot entry point: the
+// compacted copy of up to SCQMC_NOALLOC_MAX_DETS determinants (active key
+// u64, virtual codes u32, valid flag i32 = 16 B each).  Each GPU holds its own
+// copy of the array for the life of the process.  Host code must never pass
+// the array's name to a kernel (on the host it is only a stand-in symbol): its
+// device address is taken once per device with hipGetSymbolAddress, at context
+// creation with that device current, and kept in scratch_dev[].
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[(size_t)SCQMC_NOALLOC_MAX_DETS * 16];
+#define SCQ_MAX_DEVICES 64
+static std::mutex scratch_mu;
+static void *scratch_dev[SCQ_MAX_DEVICES];
+
+// device address of this device's scratch array (device must be current)
+static hipError_t scratch_address(int device, void **out) {
+    *out = nullptr;
+    if (device < 0 || device >= SCQ_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[device]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        scratch_dev[device] = p;
+    }
+    *out = scratch_dev[device];
+    return hipSuccess;
+}
+
 scqmc_status scqmc_create(int device, void *hip_stream, scqmc_ctx **out) {
     if (!out) return SCQMC_E_INVALID_ARG;
     *out = nullptr;
@@ -214,6 +246,7 @@ scqmc_status scqmc_create(int device, void *hip_stream, scqmc_ctx **out) {
     }
     c->device = device;
     if (hipSetDevice(device) != hipSuccess) { delete c; return SCQMC_E_DEVICE; }
+    if (scratch_address(device, &c->scratch_ptr) != hipSuccess) { delete c; return SCQMC_E_DEVICE; }
     if (hip_stream) {
         c->stream = (hipStream_t)hip_stream;
     } else {
@@ -1091,6 +1124,45 @@ scqmc_status scqmc_eval_snapshot(scqmc_ctx *c, int64_t n, const uint64_t *d_dets
         HIPCHK(c, hipMemcpyAsync(d_eloc_dyall, nanv.data(), sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
+    return SCQMC_OK;
+}
+
+scqmc_status scqmc_eval_snapshot_noalloc(scqmc_ctx *c, int64_t n, const uint64_t *d_dets, double *d_eloc,
+                                         double *d_psi, double *d_gamma, double *d_eloc_dyall, int32_t *d_class) {
+    if (!c) return SCQMC_E_INVALID_ARG;
+    TRY(ready_for_walkers(c));
+    if (n < 0 || (n > 0 && !d_dets)) FAIL(c, SCQMC_E_INVALID_ARG, "bad snapshot arguments");
+    if (n > SCQMC_NOALLOC_MAX_DETS)
+        FAIL(c, SCQMC_E_INVALID_ARG, "snapshot of " + std::to_string(n) + " determinants; the allocation-free entry "
+                                     "point takes at most " + std::to_string(SCQMC_NOALLOC_MAX_DETS));
+    if (c->opt.precision == 1 && c->f32_version != c->ints_version)
+        FAIL(c, SCQMC_E_STATE, "precision form: the FP32 integral copies are not made yet (any sample or "
+                               "eval_snapshot call makes them)");
+    if (!c->scratch_ptr) FAIL(c, SCQMC_E_DEVICE, "no scratch address for this device");
+    if (n == 0) return SCQMC_OK;
+    HIPCHK(c, hipSetDevice(c->device));
+    unsigned char *base = (unsigned char *)c->scratch_ptr;
+    unsigned long long *skey = (unsigned long long *)base;
+    unsigned *svirt = (unsigned *)(base + (size_t)SCQMC_NOALLOC_MAX_DETS * 8);
+    int *svalid = (int *)(base + (size_t)SCQMC_NOALLOC_MAX_DETS * 12);
+    // k_compact writes every entry i < n, so nothing has to be cleared
+    hipLaunchKernelGGL(k_compact, dim3(grid1(n, 128)), dim3(128), 0, c->stream, (const unsigned long long *)d_dets,
+                       (long long)n, c->words, c->N, c->C, c->A, c->na, c->nb, skey, svirt, svalid);
+    DevProblem P = dev_problem(c);
+    int NL = lists_per_group(c);
+    bool dy = c->opt.mode == 1 && c->has_dyall;
+    if (c->opt.precision == 1)
+        hipLaunchKernelGGL(k_eval<float>, dim3(grid1(n, WPB)), dim3(64 * WPB), kernel_lds(c), c->stream, P, skey,
+                           svirt, svalid, (long long)n, NL, d_eloc, d_psi, d_gamma, dy ? d_eloc_dyall : nullptr,
+                           (int *)d_class);
+    else
+        hipLaunchKernelGGL(k_eval<double>, dim3(grid1(n, WPB)), dim3(64 * WPB), kernel_lds(c), c->stream, P, skey,
+                           svirt, svalid, (long long)n, NL, d_eloc, d_psi, d_gamma, dy ? d_eloc_dyall : nullptr,
+                           (int *)d_class);
+    if (d_eloc_dyall && !dy)   // no Dyall energies in mode 0: NaN, filled by a kernel (no copy, no wait)
+        hipLaunchKernelGGL(k_fill_u64, dim3(grid1(n, 256)), dim3(256), 0, c->stream, (unsigned long long *)d_eloc_dyall,
+                           (long long)n, 0x7FF8000000000000ull);
+    HIPCHK(c, hipGetLastError());
     return SCQMC_OK;
 }
 

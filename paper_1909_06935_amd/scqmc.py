@@ -97,6 +97,7 @@ def lib():
             "scqmc_read_walkers": ([P, P, P, i64], C.c_int),
             "scqmc_read_counters": ([P, C.POINTER(i64), C.POINTER(i64)], C.c_int),
             "scqmc_eval_snapshot": ([P, i64, P, P, P, P, P, P], C.c_int),
+            "scqmc_eval_snapshot_noalloc": ([P, i64, P, P, P, P, P, P], C.c_int),
             "scqmc_debug_neighbors": ([P, P, i64, P, P, P, P, C.POINTER(i64)], C.c_int),
             "scqmc_save_state": ([P, P, i64, C.POINTER(i64)], C.c_int),
             "scqmc_load_state": ([P, P, i64], C.c_int),
@@ -307,6 +308,17 @@ class Engine:
         self._check(lib().scqmc_eval_snapshot(self.h, n, ptr(t), ptr(eloc), ptr(psi), ptr(gam), ptr(eld), ptr(cls)))
         self.synchronize()
         return dict(eloc=eloc, psi=psi, gamma=gam, eloc_d=eld, cls=cls)
+
+    def eval_snapshot_buffers(self, dets, out, noalloc=False):
+        """Evaluate into caller-owned device buffers (a dict of torch tensors
+        with keys eloc, psi, gamma, eloc_d, cls, each at least len(dets) long);
+        noalloc=True goes through the allocation-free entry point.  Enqueued on
+        the context stream; the caller synchronises."""
+        n = int(dets.shape[0])
+        ptr = lambda x: C.c_void_p(x.data_ptr())
+        f = lib().scqmc_eval_snapshot_noalloc if noalloc else lib().scqmc_eval_snapshot
+        self._check(f(self.h, n, ptr(dets), ptr(out["eloc"]), ptr(out["psi"]), ptr(out["gamma"]),
+                      ptr(out["eloc_d"]), ptr(out["cls"])))
 
     def debug_neighbors(self, det, cap=None):
         det = _u64(det).reshape(-1)
