@@ -206,6 +206,23 @@ scqmc_status scqmc_read_estimates(scqmc_ctx *ctx, scqmc_estimates *out);
 /* The E_var part of read_estimates alone (E_var, its jackknife error, a0^2),
  * from the per-walker sums only -- cheap enough to poll (serving loops). */
 scqmc_status scqmc_read_energy(scqmc_ctx *ctx, double *e_var, double *e_var_err, double *a0_sq);
+/* Small-norm perturber screen of "SC-NEVPT2(s)" (end of that section):
+ * classes whose sampled relative norm N_l/N_0 is below tau are left out of
+ * E^(2) (read_estimates) and of the first-order wave function
+ * (read_first_order gives them coefficient 0).  tau = 0 (the default) keeps
+ * every class.  tau must be finite and >= 0, else INVALID_ARG. */
+scqmc_status scqmc_set_nevpt2_screen(scqmc_ctx *ctx, double tau);
+/* SC-NEVPT2 first-order wave function (first equation of "SC-NEVPT2(s)"):
+ *   psi1 = sum_{l != 0} coef_l P_l H phi0,  coef_l = 1 / (E_0^(0) - E_l),
+ * for the unnormalised perturbers P_l H phi0 of a normalised phi0, with the
+ * perturber energies E_l = D_l / N_l of eq:nevpt from the sampled class sums
+ * (so that E^(2) = sum_l coef_l N_l / N_0).  Outputs, each [n] with
+ * n = n_classes - 1 in class-id order (classes 1 ..) and each optional
+ * (NULL): coef (NaN for a class never visited, 0 for a screened one),
+ * coef_err (delete-one jackknife over the walker groups of the class sums,
+ * NaN where undefined), e_l, rel_norm = N_l / N_0.  Needs mode 1; synchronises. */
+scqmc_status scqmc_read_first_order(scqmc_ctx *ctx, double *coef, double *coef_err, double *e_l, double *rel_norm,
+                                    int64_t n);
 /* Per-class sums (n == n_classes): t_l = sum t, te_l = sum t E_L,
  * n_l = sum t / c_l^2, d_l = sum t E_D,L / c_l^2 (synchronises). */
 scqmc_status scqmc_read_class_sums(scqmc_ctx *ctx, double *n_l, double *d_l, double *t_l, double *te_l, int64_t n);

@@ -66,6 +66,7 @@ struct scqmc_ctx {
     long long ncls = 0;
     scqmc_options opt{0.0, 0, 0, 0, 0};
     double e_core = 0.0, e0_ref = 0.0;
+    double tau = 0.0;   // small-norm perturber screen of SC-NEVPT2(s): classes with N_l/N_0 < tau dropped
     DBuf heff, eri, ccls, eps, refcoef, refkey;
     DBuf heff32, eri32;                  // precision form: FP32 copies
     long long ints_version = 0, f32_version = -1;
@@ -924,14 +925,16 @@ static scqmc_status download_sums(scqmc_ctx *c, std::vector<double> &ws, std::ve
     return SCQMC_OK;
 }
 
-// E^(2) of eq:nevpt2e2 from class sums N_l = sum t/c_l^2, D_l = sum t E_D,L/c_l^2
-static double e2_from_sums(const double *nl_, const double *dl_, long long n, double e0) {
+// E^(2) of eq:nevpt2e2 from class sums N_l = sum t/c_l^2, D_l = sum t E_D,L/c_l^2;
+// perturbers whose relative norm N_l/N_0 is below tau are left out (the
+// optional small-norm screen at the end of "SC-NEVPT2(s)")
+static double e2_from_sums(const double *nl_, const double *dl_, long long n, double e0, double tau) {
     double n0 = nl_[0];
     if (!(n0 > 0)) return NAN;
     double e2 = 0;
     for (long long l = 1; l < n; l++) {
         double nl = nl_[l];
-        if (nl <= 0) continue;
+        if (nl <= 0 || nl / n0 < tau) continue;
         e2 += (nl / n0) / (e0 - dl_[l] / nl);
     }
     return e2;
@@ -1004,7 +1007,7 @@ scqmc_status scqmc_read_estimates(scqmc_ctx *c, scqmc_estimates *out) {
     out->e2_err = NAN;
     if (c->opt.mode == 1 && c->has_dyall) {
         long long n = c->ncls, K = c->ncg;
-        out->e2 = e2_from_sums(&cs[2 * n], &cs[3 * n], n, c->e0_ref);
+        out->e2 = e2_from_sums(&cs[2 * n], &cs[3 * n], n, c->e0_ref, c->tau);
         // delete-one jackknife over the walker groups of the class sums
         if (K > 1 && std::isfinite(out->e2)) {
             std::vector<double> nl(n), dl(n), je(K);
@@ -1016,7 +1019,7 @@ scqmc_status scqmc_read_estimates(scqmc_ctx *c, scqmc_estimates *out) {
                     nl[l] = cs[2 * n + l] - gp[2 * n + l];
                     dl[l] = cs[3 * n + l] - gp[3 * n + l];
                 }
-                je[g] = e2_from_sums(nl.data(), dl.data(), n, c->e0_ref);
+                je[g] = e2_from_sums(nl.data(), dl.data(), n, c->e0_ref, c->tau);
                 ok = ok && std::isfinite(je[g]);
                 m += je[g];
             }
@@ -1026,6 +1029,62 @@ scqmc_status scqmc_read_estimates(scqmc_ctx *c, scqmc_estimates *out) {
                 for (long long g = 0; g < K; g++) v += (je[g] - m) * (je[g] - m);
                 out->e2_err = std::sqrt((K - 1.0) / K * v);
             }
+        }
+    }
+    return SCQMC_OK;
+}
+
+scqmc_status scqmc_set_nevpt2_screen(scqmc_ctx *c, double tau) {
+    if (!c) return SCQMC_E_INVALID_ARG;
+    if (!(tau >= 0.0) || !std::isfinite(tau)) FAIL(c, SCQMC_E_INVALID_ARG, "tau must be finite and >= 0");
+    c->tau = tau;
+    return SCQMC_OK;
+}
+
+// First-order wave function of SC-NEVPT2: psi1 = sum_l P_l H phi0 / (E_0 - E_l),
+// i.e. coefficient 1/(E_0 - E_l) for the unnormalised perturber of class l,
+// with E_l = D_l / N_l from the sampled class sums; delete-one jackknife over
+// the walker groups for the error of each coefficient.
+scqmc_status scqmc_read_first_order(scqmc_ctx *c, double *coef, double *coef_err, double *e_l, double *rel_norm,
+                                    int64_t n) {
+    if (!c) return SCQMC_E_INVALID_ARG;
+    if (!c->has_walkers) FAIL(c, SCQMC_E_STATE, "init_walkers first");
+    if (!(c->opt.mode == 1 && c->has_dyall)) FAIL(c, SCQMC_E_STATE, "needs mode 1 (set_dyall, set_options)");
+    if (n != c->ncls - 1) FAIL(c, SCQMC_E_INVALID_ARG, "n must equal n_classes - 1");
+    std::vector<double> ws, cs, gsum;
+    TRY(download_sums(c, ws, cs, &gsum));
+    long long nc = c->ncls, K = c->ncg;
+    const double *N = &cs[2 * nc], *D = &cs[3 * nc];
+    double n0 = N[0];
+    auto coef_of = [&](double nl, double dl, double base) -> double {
+        if (!(nl > 0) || !(base > 0)) return NAN;
+        if (nl / base < c->tau) return 0.0;
+        return 1.0 / (c->e0_ref - dl / nl);
+    };
+    for (long long l = 1; l < nc; l++) {
+        double x = coef_of(N[l], D[l], n0);
+        if (coef) coef[l - 1] = x;
+        if (e_l) e_l[l - 1] = N[l] > 0 ? D[l] / N[l] : NAN;
+        if (rel_norm) rel_norm[l - 1] = n0 > 0 ? N[l] / n0 : NAN;
+        if (coef_err) {
+            double err = NAN;
+            if (K > 1 && std::isfinite(x)) {
+                double m = 0, v = 0;
+                std::vector<double> je(K);
+                bool ok = true;
+                for (long long g = 0; g < K; g++) {
+                    const double *gp = &gsum[g * 4 * nc];
+                    je[g] = coef_of(N[l] - gp[2 * nc + l], D[l] - gp[3 * nc + l], n0 - gp[2 * nc]);
+                    ok = ok && std::isfinite(je[g]);
+                    m += je[g];
+                }
+                if (ok) {
+                    m /= K;
+                    for (long long g = 0; g < K; g++) v += (je[g] - m) * (je[g] - m);
+                    err = std::sqrt((K - 1.0) / K * v);
+                }
+            }
+            coef_err[l - 1] = err;
         }
     }
     return SCQMC_OK;

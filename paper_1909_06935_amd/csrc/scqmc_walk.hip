@@ -394,32 +394,39 @@ __device__ double phi1(const DevProblem &P, unsigned long long y, int s, int sg,
     // Doubles {t,u} -> {s, r}.  With Q1 < Q2 the sorted pair, the element is
     // (Q1 P1|Q2 P2) - (Q1 P2|Q2 P1) = sgn [(s p1|r p2) - (s p2|r p1)] with
     // sgn = +1 when s precedes r, each term present only for matching spins;
-    // read as (p2 r|p1 s) and (p1 r|p2 s) so that the virtual s, the only
-    // index that differs between the rows of a group, is the last one.
+    // read as (p2 r|p1 s) = J and (p1 r|p2 s) = K so that the virtual s, the
+    // only index that differs between the rows of a group, is the last one.
+    //
+    // Everything but the integrals is fixed per list (per r).  The reference
+    // determinant d = y - r + t + u has the same electrons per spin as m, so
+    // the number of alpha electrons among t < u is [s alpha] + [r alpha]:
+    //   s, r of one spin:  t, u of that spin, element K - J;
+    //   s alpha, r beta:   t alpha, u beta, element J (s precedes r);
+    //   s beta, r alpha:   t alpha, u beta, element K.
+    // The sign is (-1)^e, e = b(Q1) + b(Q2) - sum_Q [(P1 < Q) + (P2 < Q)] with
+    // b(Q) the electrons of d below Q: b(s) = bs; b(r) = (electrons of y
+    // below r) + [t < r] + [u < r], whose last two terms cancel (P < r);
+    // (P < s) is 1 for every active P when s is beta and [P alpha] when s is
+    // alpha.  So e = bs + (electrons of y below r) + [s alpha, r beta] mod 2.
+    // (The part of the phase that depends on d alone is folded into the
+    // stored coefficient.)
+    // With a wave-uniform group (U) the list entries are scalars: the
+    // integrals of eight entries are requested before any is used, so their
+    // loads overlap.  Same order of additions as one entry at a time.
     unsigned Np = (unsigned)P.Np, N2 = Np * Np, N3 = N2 * Np;
     unsigned sp = (unsigned)g_idx(P, gs);
     const R *E = Ints<R>::eri(P);
-    // The sign: with Q1 < Q2 the added pair {s, r}, b(Q) the electrons of the
-    // reference determinant below Q, (-1)^e with
-    // e = b(Q1) + b(Q2) - sum_{Q in {Q1,Q2}} [(P1 < Q) + (P2 < Q)]
-    //   = bs + br - [(P1 < s) + (P2 < s) + (P1 < r) + (P2 < r)]
-    // (symmetric in Q1, Q2).  An active P precedes the virtual s when P is
-    // alpha or s is beta; s precedes r exactly when s is alpha and r beta.
-    // With a wave-uniform group (U) the list entries are scalars: the
-    // integrals of eight entries are requested before any is used, so their
-    // loads overlap (J and K are both read; the spin conditions select
-    // afterwards).  Same order of additions as one entry at a time.
     constexpr int P1UNR = (U ? 8 : 1);
     for (int li = 1; li <= nl; li++) {
         uint2 ox = lists(li);
         unsigned cnt = ox.y & 0xFFFFFFu;
         if (!cnt) continue;
         int r = (int)(ox.y >> 24);
-        int gr = g_of_active(P, r);
         int sr = r >> 5;                         // spin of r
-        bool s_first = (sg == 0) && (sr == 1);
-        unsigned rr = (unsigned)(r & 31);
-        unsigned long long yr = y & ~(1ull << r);
+        bool needJ = !(sg == 1 && sr == 0), needK = !(sg == 0 && sr == 1);
+        R jsign = (sg == sr) ? R(-1) : R(1);
+        bool neg = ((bs + key_below(y, r) + (sg == 0 && sr == 1)) & 1) != 0;
+        const R *Er = E + (unsigned)(r & 31) * N2 + sp;
         unsigned k = 0;
         if (P1UNR > 1) {
             for (; k + P1UNR <= cnt; k += P1UNR) {
@@ -434,21 +441,15 @@ __device__ double phi1(const DevProblem &P, unsigned long long y, int s, int sg,
 #pragma unroll
                 for (int j = 0; j < P1UNR; j++) {
                     unsigned q1 = (cd[j] >> 6) & 31u, q2 = cd[j] & 31u;
-                    Jv[j] = E[q2 * N3 + rr * N2 + q1 * Np + sp];
-                    Kv[j] = E[q1 * N3 + rr * N2 + q2 * Np + sp];
+                    Jv[j] = needJ ? Er[q2 * N3 + q1 * Np] : R(0);
+                    Kv[j] = needK ? Er[q1 * N3 + q2 * Np] : R(0);
                 }
 #pragma unroll
                 for (int j = 0; j < P1UNR; j++) {
                     int t = (int)(cd[j] >> 6), u = (int)(cd[j] & 63u);
-                    if (t == r || u == r) continue;
-                    int P1 = g_of_active(P, t), P2 = g_of_active(P, u);
-                    int st = t >> 5, su = u >> 5;
-                    int br = key_below(yr | (1ull << t) | (1ull << u), r);
-                    int e = bs + br - ((st == 0 || sg == 1) + (su == 0 || sg == 1) + (P1 < gr) + (P2 < gr));
-                    R J = (st == sg && su == sr) ? Jv[j] : R(0);
-                    R K = (su == sg && st == sr) ? Kv[j] : R(0);
-                    double el = (double)(s_first ? J - K : K - J);
-                    acc += (e & 1) ? -wv[j] * el : wv[j] * el;
+                    if (t == r || u == r) continue;   // a single y -> y + u, summed with the y-list
+                    double el = (double)(Kv[j] + jsign * Jv[j]);
+                    acc += neg ? -wv[j] * el : wv[j] * el;
                 }
             }
         }
@@ -457,15 +458,11 @@ __device__ double phi1(const DevProblem &P, unsigned long long y, int s, int sg,
             int t = (int)(code >> 6), u = (int)(code & 63u);
             if (t == r || u == r) continue;
             double w = tload<U>(P.xtab.vals, ox.x + k);
-            int P1 = g_of_active(P, t), P2 = g_of_active(P, u);
-            int st = t >> 5, su = u >> 5;
-            int br = key_below(yr | (1ull << t) | (1ull << u), r);
-            int e = bs + br - ((st == 0 || sg == 1) + (su == 0 || sg == 1) + (P1 < gr) + (P2 < gr));
-            unsigned p1 = (unsigned)(t & 31), p2 = (unsigned)(u & 31);
-            R J = (st == sg && su == sr) ? E[p2 * N3 + rr * N2 + p1 * Np + sp] : R(0);
-            R K = (su == sg && st == sr) ? E[p1 * N3 + rr * N2 + p2 * Np + sp] : R(0);
-            double el = (double)(s_first ? J - K : K - J);
-            acc += (e & 1) ? -w * el : w * el;
+            unsigned q1 = (unsigned)(t & 31), q2 = (unsigned)(u & 31);
+            R J = needJ ? Er[q2 * N3 + q1 * Np] : R(0);
+            R K = needK ? Er[q1 * N3 + q2 * Np] : R(0);
+            double el = (double)(K + jsign * J);
+            acc += neg ? -w * el : w * el;
         }
     }
     return acc;
@@ -694,7 +691,11 @@ __device__ __forceinline__ uint2 view_list(const GroupView &v, int k) {
     return o;
 }
 
-// row d of group G: <m|H|n>, psi(m), the Dyall element if m keeps n's virtual set
+// row d of group G: <m|H|n>, psi(m), the Dyall element if m keeps n's virtual set.
+// R is the precision of the two-electron terms of psi(m) (the doubles of the
+// reference expansion); <m|H|n> and the one-body (Fock) elements inside psi(m)
+// are FP64 in both forms: they are few per row and the largest terms, so
+// they would carry most of the FP32 rounding of a local energy.
 template <int VP, bool U, class R>
 __device__ __forceinline__ void row_eval(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L,
                                          const RowDec &d, const GroupView &G, RowRes &o) {
@@ -710,14 +711,14 @@ __device__ __forceinline__ void row_eval(const DevProblem &P, const WalkerCtx &W
         double ph = wphase_single(L, Pr0, Qa0);
         double act;
         o.phase = ph;
-        o.hnm = ph * single_elem_w2<R>(P, W, L, Pr0, Qa0, d.vq, &act);
+        o.hnm = ph * single_elem_w2<double>(P, W, L, Pr0, Qa0, d.vq, &act);
         o.hd = ph * act;
     } else {
         double ph = wphase_double(L, Pr0, Pr1, Qa0, Qa1);
         o.phase = ph;
         // the lane-varying virtual, when the row adds one, is read as the last index
-        double e = (d.vq >= 0) ? (double)double_elem_x<R>(P, Pr0, Pr1, Qa0, Qa1, g_idx(P, Qa1) == d.vq)
-                               : (double)double_elem<R>(P, Pr0, Pr1, Qa0, Qa1);
+        double e = (d.vq >= 0) ? double_elem_x<double>(P, Pr0, Pr1, Qa0, Qa1, g_idx(P, Qa1) == d.vq)
+                               : double_elem<double>(P, Pr0, Pr1, Qa0, Qa1);
         o.hnm = ph * e;
         o.hd = o.hnm;
         if (P.eps_screen > 0.0 && !(fabs(o.hnm) > P.eps_screen)) { o.ok = false; o.psi = 0.0; return; }
@@ -730,7 +731,9 @@ __device__ __forceinline__ void row_eval(const DevProblem &P, const WalkerCtx &W
         // same for every row of the wave: a scalar
         phi = phi1<U, R>(P, G.xkey, d.Lp0, uni((int)(d.Lp0 >= P.V)), G.nl,
                          [&](int k) -> uint2 { return view_list<U>(G, k); },
-                         [&](int gT, int gS) -> double { return fock_y<R>(P, W, L, G.rg0, G.rg1, G.pg0, G.pg1, gT, gS); });
+                         [&](int gT, int gS) -> double {
+                             return fock_y<double>(P, W, L, G.rg0, G.rg1, G.pg0, G.pg1, gT, gS);
+                         });
     } else {
         phi = phi2<U, R>(P, d.Lp0, d.Lp1, view_list<U>(G, 0), d.vq);
     }
@@ -848,8 +851,48 @@ __device__ __forceinline__ double subwave_sum(double v, unsigned S) {
     return v;
 }
 
+// rows r0 + t*S + (lane mod S), t < ntile, of the live groups (S lanes per
+// group, 64/S groups per pass): group data differs between sub-waves
+template <class R>
+__device__ __forceinline__ void subwave_rows(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, int lane,
+                                             const Block &b, int vp, bool dy, unsigned S, unsigned r0, unsigned ntile,
+                                             unsigned nlive, RowDec &d, bool decoded, Acc &a) {
+    int sh = __ffs(S) - 1;
+    unsigned gpi = WAVE >> sh;
+    unsigned sub = (unsigned)lane & (S - 1), grp = (unsigned)lane >> sh;
+    for (unsigned t = 0; t < ntile; t++) {
+        unsigned r = r0 + t * S + sub;
+        bool rv = r < b.R;
+        if (!decoded && rv) row_decode(P, W, b, r, d);
+        for (unsigned gp = 0; gp < nlive; gp += gpi) {
+            unsigned gc = gp + grp;
+            unsigned gi = gc < nlive ? L.perm[gc] : 0u;
+            double v = 0.0;
+            if (rv && gc < nlive) {
+                RowRes o;
+                GroupView gv = group_view<false>(L, gi);
+                row_eval_any<false, R>(P, W, L, vp, d, gv, o);
+                if (o.ok) {
+                    a.E += o.hnm * o.psi;
+                    v = fabs(o.psi);
+                    a.G += v;
+                    if (dy && d.same) a.D += o.hd * o.psi;
+                }
+            }
+            v = subwave_sum(v, S);
+            if (sub == 0 && gc < nlive) L.G[gi].gam += v;
+            __syncwarp();
+        }
+    }
+}
+
 // sweep one block: 64 groups set up at a time, each group owns a sub-wave of
-// S lanes, lane row index r = tile*S + (lane mod S) fixed across groups
+// S lanes, lane row index r = tile*S + (lane mod S) fixed across groups.
+// Groups of more than 32 rows own the whole wave (wave-uniform group data,
+// 64-row tiles); a last tile of at most 32 rows is not given a whole wave
+// per group but goes, for several groups at once, to sub-waves of 16 or 32
+// lanes (the blocks with one virtual electron added have 75 or 76 rows:
+// 64 + 11 or 12).
 template <bool MOVE, class R>
 __device__ void sweep_block(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, int lane, const Block &b,
                             uint32_t wid, uint32_t step, bool dy, Acc &a) {
@@ -858,10 +901,13 @@ __device__ void sweep_block(const DevProblem &P, const WalkerCtx &W, const WaveL
     unsigned S = 1;
     while (S < b.R && S < WAVE) S <<= 1;
     int sh = __ffs(S) - 1;
-    unsigned gpi = WAVE >> sh;                 // groups per pass
     unsigned ntile = (b.R + S - 1) >> sh;      // > 1 only when R > 64
-    unsigned sub = (unsigned)lane & (S - 1), grp = (unsigned)lane >> sh;
+    unsigned sub = (unsigned)lane & (S - 1);
     int vp = b.vp[0] + b.vp[1];
+    // wave-uniform tiles and the short last tile (S == WAVE only)
+    unsigned tail = b.R - WAVE * (ntile - 1);
+    unsigned ntu = (S == WAVE && ntile > 1 && tail <= 32) ? ntile - 1 : ntile;
+    unsigned St = tail <= 16 ? 16u : 32u;
     RowDec d;
     if (ntile == 1 && sub < b.R) row_decode(P, W, b, sub, d);
     for (unsigned gb = 0; gb < b.ng; gb += WAVE) {
@@ -879,7 +925,7 @@ __device__ void sweep_block(const DevProblem &P, const WalkerCtx &W, const WaveL
         __syncwarp();
         if (S == WAVE) {
             // one group per pass: its data is wave-uniform
-            for (unsigned t = 0; t < ntile; t++) {
+            for (unsigned t = 0; t < ntu; t++) {
                 unsigned r = t * WAVE + sub;
                 bool rv = r < b.R;
                 if (ntile > 1 && rv) row_decode(P, W, b, r, d);
@@ -902,31 +948,12 @@ __device__ void sweep_block(const DevProblem &P, const WalkerCtx &W, const WaveL
                     __syncwarp();
                 }
             }
-        } else
-        for (unsigned t = 0; t < ntile; t++) {
-            unsigned r = t * S + sub;
-            bool rv = r < b.R;
-            if (ntile > 1 && rv) row_decode(P, W, b, r, d);
-            for (unsigned gp = 0; gp < nlive; gp += gpi) {
-                unsigned gc = gp + grp;
-                unsigned gi = gc < nlive ? L.perm[gc] : 0u;
-                double v = 0.0;
-                if (rv && gc < nlive) {
-                    RowRes o;
-                    GroupView gv = group_view<false>(L, gi);
-                    row_eval_any<false, R>(P, W, L, vp, d, gv, o);
-                    if (o.ok) {
-                        a.E += o.hnm * o.psi;
-                        v = fabs(o.psi);
-                        a.G += v;
-                        if (dy && d.same) a.D += o.hd * o.psi;
-                    }
-                }
-                v = subwave_sum(v, S);
-                if (sub == 0 && gc < nlive) L.G[gi].gam += v;
-                __syncwarp();
-            }
         }
+        // sub-wave groups: all rows of small blocks, or the short last tile
+        unsigned nts = S == WAVE ? ntile - ntu : ntile;
+        if (nts)
+            subwave_rows<R>(P, W, L, lane, b, vp, dy, S == WAVE ? St : S, S == WAVE ? WAVE * ntu : 0u, nts, nlive,
+                            d, S != WAVE && ntile == 1, a);
         if (MOVE && g < b.ng && mg.gam > 0.0) {
             double tau = exp_draw(P.seed, wid, step, 0u, (uint32_t)mg.xkey, (uint32_t)(mg.xkey >> 32)) / mg.gam;
             if (tau < a.best || (tau == a.best && mg.xkey < a.bestkey)) {

@@ -93,6 +93,8 @@ def lib():
             "scqmc_synchronize": ([P], C.c_int),
             "scqmc_read_estimates": ([P, C.POINTER(Estimates)], C.c_int),
             "scqmc_read_class_sums": ([P, P, P, P, P, i64], C.c_int),
+            "scqmc_set_nevpt2_screen": ([P, dbl], C.c_int),
+            "scqmc_read_first_order": ([P, P, P, P, P, i64], C.c_int),
             "scqmc_read_walker_sums": ([P, P, P, P, i64], C.c_int),
             "scqmc_read_walkers": ([P, P, P, i64], C.c_int),
             "scqmc_read_counters": ([P, C.POINTER(i64), C.POINTER(i64)], C.c_int),
@@ -269,6 +271,16 @@ class Engine:
         out = [np.zeros(n) for _ in range(4)]
         self._check(lib().scqmc_read_class_sums(self.h, *[_p(a) for a in out], n))
         return dict(n=out[0], d=out[1], t=out[2], te=out[3])
+
+    def set_nevpt2_screen(self, tau):
+        self._check(lib().scqmc_set_nevpt2_screen(self.h, float(tau)))
+
+    def read_first_order(self):
+        """SC-NEVPT2 first-order coefficients of classes 1..: dict(coef, coef_err, e_l, rel_norm)."""
+        n = self.n_classes - 1
+        out = [np.zeros(max(n, 1)) for _ in range(4)]
+        self._check(lib().scqmc_read_first_order(self.h, *[_p(a) for a in out], n))
+        return dict(coef=out[0][:n], coef_err=out[1][:n], e_l=out[2][:n], rel_norm=out[3][:n])
 
     def read_walker_sums(self):
         W = self.n_walkers

@@ -73,7 +73,10 @@ def _n_nbr(sp, d):
     return brute.count_neighbors(A, sp.n_virt, a_occ, list(virtual_count(sp, d)))
 
 
-def test_cfg3_equilibrated_snapshot_1k(cfg3):
+@pytest.fixture(scope="module")
+def cfg3_snap(cfg3):
+    """1,000 equilibrated walkers (every active-space walker up to 40 of
+    them, the rest drawn at random) and the oracle's evaluation of them."""
     prob, eng, orc, eq = cfg3
     sp = prob.space
     kinds = np.array([sum(_kind(sp, d)) for d in eq])
@@ -86,13 +89,43 @@ def test_cfg3_equilibrated_snapshot_1k(cfg3):
     dets = eq[idx]
     _say(f"cfg3 snapshot: {len(cas)} active-space, {np.sum(kinds[rest] == 1)} one-virtual, "
          f"{np.sum(kinds[rest] == 2)} two-virtual walkers; oracle on {THREADS} threads")
-    from test_gpu_parity import compare_eval
-    g = eng.eval_snapshot(dets)
     ref = orc.eval(dets, nthreads=THREADS)
     nn = np.array([_n_nbr(sp, d) for d in dets])
-    st = compare_eval(g, ref, nn, "cfg3 1k equilibrated")
+    return dets, ref, nn
+
+
+def test_cfg3_equilibrated_snapshot_1k(cfg3, cfg3_snap):
+    prob, eng, orc, eq = cfg3
+    dets, ref, nn = cfg3_snap
+    from test_gpu_parity import compare_eval
+    st = compare_eval(eng.eval_snapshot(dets), ref, nn, "cfg3 1k equilibrated")
     # walkers are drawn with probability psi^2: none sits on a numerically zero overlap
     assert st["excluded"] == 0 and st["n"] == 1000, st
+
+
+def test_cfg3_precision_form_snapshot_1k(cfg3, cfg3_snap):
+    """The precision form (FP32 two-electron terms of the overlaps, FP64 for
+    <m|H|n>, the Fock elements, psi(n) and every sum) on the same 1,000
+    equilibrated walkers against the FP64 oracle: every local energy and
+    Dyall local energy within the FP32 rounding bound 2^-24 (S_abs + |E| kappa)
+    + 1e-12 (derived from the arithmetic; see test_gpu_fp32); the error
+    distribution and the count above 1e-6 Eh are printed."""
+    from paper_1909_06935_amd.scqmc import Engine
+    prob, _, orc, eq = cfg3
+    dets, ref, nn = cfg3_snap
+    e32 = Engine.from_problem(prob, mode=1)
+    e32.set_options(mode=1, precision=1)
+    g = {k: v.cpu().numpy() for k, v in e32.eval_snapshot(dets).items()}
+    scale = np.abs(ref["psi"]).max()
+    assert np.all(np.abs(g["psi"] - ref["psi"]) <= 1e-12 * scale)
+    for key, label in (("eloc", "E_L"), ("eloc_d", "E_D,L")):
+        ok = ~np.isnan(ref[key])
+        err = np.abs(g[key] - ref[key])[ok]
+        bound = 2.0 ** -24 * (ref["sabs"] + np.abs(ref[key]) * ref["kappa"])[ok] + 1e-12
+        _say(f"cfg3 precision form {label}: {ok.sum()} compared, |dE| median {np.median(err):.2e}, "
+             f"p99 {np.quantile(err, 0.99):.2e}, max {err.max():.2e}, above 1e-6 Eh: {(err > 1e-6).sum()}, "
+             f"S_abs up to {ref['sabs'][ok].max():.2e} Eh, largest error / rounding bound {np.max(err / bound):.3f}")
+        assert np.all(err <= bound), (label, np.max(err / bound))
 
 
 def _neighbor_table(nb, W2):

@@ -242,3 +242,55 @@ def test_error_bar_calibration_50_seeds_cfg1():
              f"chi^2/49 = {chi:.2f}")
         assert 0.52 <= chi <= 1.75, (k, chi)
         assert abs(x.mean() - exact) <= 4.0 * sem, (k, x.mean(), exact, sem)
+
+
+def test_sc_nevpt2_first_order_and_screen_cfg1():
+    """SC-NEVPT2 first-order wave function and the small-norm screen
+    ("SC-NEVPT2(s)") against the brute-force definitions on the 12-orbital
+    system: for every class the walk visited, the sampled perturber energy
+    E_l and the coefficient 1/(E_0 - E_l) agree with the exact ones within 5
+    of their jackknife errors (plus 1e-9); sum_l coef_l N_l/N_0 equals the
+    reported E^(2); with a screen tau that falls in a gap of the exact norms,
+    E^(2) drops exactly the classes below tau and agrees with the exact
+    screened E^(2) within 6 of its error."""
+    prob = cfg1_problem()
+    _say("cfg1 first-order wave function")
+    b = brute.Brute(prob, wl.dense_eri(prob.chol), eps_virt=prob.eps_virt)
+    eng = _engine(prob, mode=1, burn_in=100, block_len=100)
+    eng.init_walkers(wl.draw_walkers(prob.ref_dets, prob.ref_coeff, 256, prob.seed_walk), prob.seed_walk)
+    eng.sample(2100)
+    fo = eng.read_first_order()
+    est = eng.read_estimates()
+    e0 = b.e0
+    seen = np.isfinite(fo["coef"])
+    assert seen.sum() >= 20, seen.sum()
+    n_checked = 0
+    for l in np.nonzero(seen)[0]:
+        cls = int(l) + 1
+        assert cls in b.energies, cls          # a visited class has a nonzero perturber
+        c_ex = 1.0 / (e0 - b.energies[cls])
+        err = fo["coef_err"][l]
+        if not np.isfinite(err):
+            continue
+        assert abs(fo["coef"][l] - c_ex) <= 5 * err + 1e-9, (cls, fo["coef"][l], c_ex, err)
+        n_checked += 1
+    _say(f"first-order coefficients: {seen.sum()} classes visited, {n_checked} checked against 1/(E_0 - E_l)")
+    assert n_checked >= 20
+    e2_from_coef = float(np.nansum(fo["coef"] * fo["rel_norm"]))
+    assert abs(e2_from_coef - est["e2"]) <= 1e-10 * max(1.0, abs(est["e2"]))
+    # a screen in the widest gap (in log norm) of the exact relative norms
+    norms = np.array(sorted(b.norms.values()))
+    lg = np.log(norms)
+    k = int(np.argmax(np.diff(lg)[len(lg) // 4: 3 * len(lg) // 4])) + len(lg) // 4
+    tau = float(np.exp(0.5 * (lg[k] + lg[k + 1])))
+    eng.set_nevpt2_screen(tau)
+    est2 = eng.read_estimates()
+    fo2 = eng.read_first_order()
+    kept = fo2["rel_norm"] >= tau
+    assert np.all(fo2["coef"][~kept & np.isfinite(fo2["rel_norm"]) & (fo2["rel_norm"] > 0)] == 0.0)
+    e2_ex = sum(nl / (e0 - b.energies[l]) for l, nl in b.norms.items() if nl >= tau)
+    _say(f"screen tau {tau:.3e}: E2 {est2['e2']:.6f} +- {est2['e2_err']:.6f}, exact screened {e2_ex:.6f}, "
+         f"unscreened {est['e2']:.6f}")
+    assert abs(est2["e2"] - e2_ex) < 6 * est2["e2_err"], (est2, e2_ex)
+    eng.set_nevpt2_screen(0.0)
+    assert eng.read_estimates()["e2"] == est["e2"]
