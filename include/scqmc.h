@@ -312,10 +312,21 @@ scqmc_status scqmc_batch_set_schedule(scqmc_batch *batch, int32_t order, int32_t
  * consecutive slots from a device counter until the schedule is exhausted.
  * Results are the same either way.  bin 0..4096, else INVALID_ARG. */
 scqmc_status scqmc_batch_set_queue(scqmc_batch *batch, int32_t bin);
+/* Kernel variant of the hardware-dispatched launch: walkers (waves) per
+ * workgroup and the minimum waves per SIMD the kernel's register budget is
+ * compiled for.  Supported pairs: (1, 3), (1, 4) [default], (1, 5), (2, 4),
+ * (4, 4); others -> INVALID_ARG.  The precision form has (1, 4) only (a batch
+ * in the precision form with another pair fails at launch with
+ * UNSUPPORTED).  Results do not depend on the variant. */
+scqmc_status scqmc_batch_set_kernel(scqmc_batch *batch, int32_t walkers_per_group, int32_t waves_per_simd);
+scqmc_status scqmc_batch_get_kernel(const scqmc_batch *batch, int32_t *walkers_per_group, int32_t *waves_per_simd);
 /* Autotuner: times trial_steps steps (real steps of every system) for each
  * order 0..2, 1, 2, 4 steps per launch and hand-out bin 0 (hardware), 1, 4
- * (persistent) and keeps the fastest; outputs the choice and its time per
- * step (each optional). */
+ * (persistent) with the default kernel variant, then -- if the hardware
+ * hand-out won and the batch is FP64 -- each other kernel variant of
+ * scqmc_batch_set_kernel at that schedule, and keeps the fastest; outputs the
+ * schedule and its time per step (each optional); the kernel variant chosen
+ * is read with scqmc_batch_get_kernel. */
 scqmc_status scqmc_batch_tune(scqmc_batch *batch, int64_t trial_steps, int32_t *order, int32_t *steps_per_launch,
                               int32_t *bin, double *ms_per_step);
 

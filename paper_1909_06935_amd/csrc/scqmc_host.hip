@@ -1438,6 +1438,8 @@ struct scqmc_batch {
     int spl = 1;            // steps per launch
     int bin = 0;            // 0: hardware dispatch of the slots; >= 1: persistent grid, work items of bin slots
     int ncu = 0;            // compute units of the device (persistent grid size)
+    int wpg = 1;            // walkers (waves) per workgroup of the hardware-dispatched launch: 1, 2, 4
+    int wps = 4;            // minimum waves per SIMD the kernel is compiled for: 3, 4, 5 (wpg 1 only)
     long long nslots = 0;
     std::vector<long long> Ws;
     int sched_order = -1;
@@ -1446,7 +1448,7 @@ struct scqmc_batch {
     size_t lds = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
-    int graph_spl = 0, graph_bin = -1;
+    int graph_spl = 0, graph_bin = -1, graph_wpg = 0, graph_wps = 0;
     long long graph_slots = -1;
 };
 
@@ -1563,14 +1565,31 @@ scqmc_status batch_upload(scqmc_batch *b) {
         BHIP(b, hipMemset(b->dhead.p, 0, sizeof(unsigned)));
         BHIP(b, hipDeviceSynchronize());
     }
-    b->lds = WPB * wave_lds_bytes(NLmax);
+    b->lds = wave_lds_bytes(NLmax);   // per wave; a workgroup of wpg walkers takes wpg times this
     return SCQMC_OK;
+}
+
+// the hardware-dispatched batch kernel for (precision, walkers per workgroup,
+// waves per SIMD); FP32 has the default variant only
+using BatchKernel = void (*)(const BatchSys *, const int *, const int *, long long, int, unsigned);
+static BatchKernel batch_kernel(int precision, int wpg, int wps) {
+    if (precision == 1) return (wpg == 1 && wps == 4) ? k_sample_batch<float, 1, 4> : nullptr;
+    if (wps == 4) {
+        if (wpg == 1) return k_sample_batch<double, 1, 4>;
+        if (wpg == 2) return k_sample_batch<double, 2, 4>;
+        if (wpg == 4) return k_sample_batch<double, 4, 4>;
+        return nullptr;
+    }
+    if (wpg != 1) return nullptr;
+    if (wps == 3) return k_sample_batch<double, 1, 3>;
+    if (wps == 5) return k_sample_batch<double, 1, 5>;
+    return nullptr;
 }
 
 scqmc_status batch_launch(scqmc_batch *b, int nsteps) {
     int n = (int)b->ctx.size();
-    dim3 grid(grid1(b->nslots, WPB)), blk(64 * WPB);
     if (b->bin > 0) {
+        dim3 blk(64);
         // persistent grid: sixteen workgroups (four waves per SIMD) per compute unit
         long long items = (b->nslots + b->bin - 1) / b->bin;
         long long g = std::min<long long>(items, 16LL * std::max(1, b->ncu));
@@ -1588,13 +1607,13 @@ scqmc_status batch_launch(scqmc_batch *b, int nsteps) {
         BHIP(b, hipGetLastError());
         return SCQMC_OK;
     }
+    BatchKernel kern = batch_kernel(b->precision, b->wpg, b->wps);
+    if (!kern) BFAIL(b, SCQMC_E_UNSUPPORTED, "no batch kernel for this precision / walkers per workgroup / waves");
+    dim3 grid(grid1(b->nslots, b->wpg)), blk(64 * b->wpg);
     hipLaunchKernelGGL(k_order_batch, dim3(n), dim3(1024), 0, b->stream, b->dsys.as<const BatchSys>());
-    if (b->precision == 1)
-        hipLaunchKernelGGL(k_sample_batch<float>, grid, blk, b->lds, b->stream, b->dsys.as<const BatchSys>(),
-                           b->dslot_sys.as<const int>(), b->dslot_w.as<const int>(), b->nslots, nsteps);
-    else
-        hipLaunchKernelGGL(k_sample_batch<double>, grid, blk, b->lds, b->stream, b->dsys.as<const BatchSys>(),
-                           b->dslot_sys.as<const int>(), b->dslot_w.as<const int>(), b->nslots, nsteps);
+    hipLaunchKernelGGL(kern, grid, blk, b->lds * b->wpg, b->stream, b->dsys.as<const BatchSys>(),
+                       b->dslot_sys.as<const int>(), b->dslot_w.as<const int>(), b->nslots, nsteps,
+                       (unsigned)b->lds);
     hipLaunchKernelGGL(k_batch_advance, dim3(grid1(n, 64)), dim3(64), 0, b->stream, b->dsys.as<BatchSys>(), n, nsteps,
                        (unsigned *)nullptr);
     BHIP(b, hipGetLastError());
@@ -1604,7 +1623,9 @@ scqmc_status batch_launch(scqmc_batch *b, int nsteps) {
 // one graph per (steps per launch, schedule): a batched launch and the step
 // advance, replayed as many times as needed
 scqmc_status batch_graph(scqmc_batch *b) {
-    if (b->gexec && b->graph_spl == b->spl && b->graph_slots == b->nslots && b->graph_bin == b->bin) return SCQMC_OK;
+    if (b->gexec && b->graph_spl == b->spl && b->graph_slots == b->nslots && b->graph_bin == b->bin &&
+        b->graph_wpg == b->wpg && b->graph_wps == b->wps)
+        return SCQMC_OK;
     free_graph(b);
     BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     scqmc_status st = batch_launch(b, b->spl);
@@ -1617,6 +1638,8 @@ scqmc_status batch_graph(scqmc_batch *b) {
     b->graph_spl = b->spl;
     b->graph_slots = b->nslots;
     b->graph_bin = b->bin;
+    b->graph_wpg = b->wpg;
+    b->graph_wps = b->wps;
     return SCQMC_OK;
 }
 
@@ -1700,6 +1723,8 @@ scqmc_status scqmc_batch_tune(scqmc_batch *b, int64_t trial_steps, int32_t *orde
     b->precision = b->ctx[0]->opt.precision;
     const int orders[3] = {0, 1, 2}, spls[3] = {1, 2, 4}, bins[3] = {0, 1, 4};
     double best = 1e300;
+    b->wpg = 1;
+    b->wps = 4;
     int bo = 0, bs = 1, bb = 0;
     for (int o : orders)
         for (int sp : spls)
@@ -1721,6 +1746,27 @@ scqmc_status scqmc_batch_tune(scqmc_batch *b, int64_t trial_steps, int32_t *orde
     b->order = bo;
     b->spl = bs;
     b->bin = bb;
+    // second phase, hardware hand-out only: walkers per workgroup and the
+    // waves-per-SIMD register budget of the kernel (FP64; the precision form
+    // has the default variant only)
+    int bw = 1, bv = 4;
+    if (bb == 0 && b->precision == 0) {
+        const int kv[4][2] = {{2, 4}, {4, 4}, {1, 3}, {1, 5}};
+        for (const auto &k : kv) {
+            b->wpg = k[0];
+            b->wps = k[1];
+            long long nst = ((trial_steps + bs - 1) / bs) * bs;
+            scqmc_status st = batch_run(b, bs);
+            if (st != SCQMC_OK) return st;
+            auto t0 = std::chrono::steady_clock::now();
+            st = batch_run(b, nst);
+            if (st != SCQMC_OK) return st;
+            double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / nst;
+            if (ms < best) { best = ms; bw = k[0]; bv = k[1]; }
+        }
+    }
+    b->wpg = bw;
+    b->wps = bv;
     if (order) *order = bo;
     if (steps_per_launch) *steps_per_launch = bs;
     if (bin) *bin = bb;
@@ -1734,6 +1780,22 @@ scqmc_status scqmc_batch_set_schedule(scqmc_batch *b, int32_t order, int32_t ste
         BFAIL(b, SCQMC_E_INVALID_ARG, "order must be 0..2, steps_per_launch 1..1024");
     b->order = order;
     b->spl = steps_per_launch;
+    return SCQMC_OK;
+}
+
+scqmc_status scqmc_batch_set_kernel(scqmc_batch *b, int32_t walkers_per_group, int32_t waves_per_simd) {
+    if (!b) return SCQMC_E_INVALID_ARG;
+    if (!batch_kernel(0, walkers_per_group, waves_per_simd))
+        BFAIL(b, SCQMC_E_INVALID_ARG, "supported: (1, 3), (1, 4), (1, 5), (2, 4), (4, 4)");
+    b->wpg = walkers_per_group;
+    b->wps = waves_per_simd;
+    return SCQMC_OK;
+}
+
+scqmc_status scqmc_batch_get_kernel(const scqmc_batch *b, int32_t *walkers_per_group, int32_t *waves_per_simd) {
+    if (!b) return SCQMC_E_INVALID_ARG;
+    if (walkers_per_group) *walkers_per_group = b->wpg;
+    if (waves_per_simd) *waves_per_simd = b->wps;
     return SCQMC_OK;
 }
 

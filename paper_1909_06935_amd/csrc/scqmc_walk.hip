@@ -1347,13 +1347,20 @@ __global__ __launch_bounds__(1024) void k_order_batch(const BatchSys *sys) {
     order_walkers(B.S.virt, B.W, B.order);
 }
 
-// slot -> (system, rank): the rank's walker comes from the system's order
-template <class R>
-__global__ __launch_bounds__(64 * WPB, 4) void k_sample_batch(const BatchSys *sys, const int *slot_sys,
-                                                         const int *slot_w, long long nslots, int nsteps) {
+// slot -> (system, rank): the rank's walker comes from the system's order.
+// NW walkers (waves) per workgroup and at least MINW waves per SIMD (the
+// register budget the compiler works to) are the two kernel parameters the
+// batched form's autotuner chooses among.
+// The waves of a workgroup may walk walkers of different systems, whose LDS
+// layouts differ in size: each wave's region starts at wave * wstride, wstride
+// = the LDS of the largest layout of the batch.
+template <class R, int NW, int MINW>
+__global__ __launch_bounds__(64 * NW, MINW) void k_sample_batch(const BatchSys *sys, const int *slot_sys,
+                                                              const int *slot_w, long long nslots, int nsteps,
+                                                              unsigned wstride) {
     extern __shared__ unsigned char smem[];
     int wave = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
-    long long slot = (long long)blockIdx.x * WPB + wave;
+    long long slot = (long long)blockIdx.x * NW + wave;
     if (slot >= nslots) return;
     int s = uni(slot_sys[slot]);
     const BatchSys &B = sys[s];
@@ -1361,7 +1368,7 @@ __global__ __launch_bounds__(64 * WPB, 4) void k_sample_batch(const BatchSys *sy
     DevProblem P = B.P;
     WalkerArrays S = B.S;
     int NL = uni(B.NL);
-    WaveLDS L = carve(smem + wave * wave_lds_bytes(NL), NL);
+    WaveLDS L = carve(smem + wave * wstride, NL);
     long long Wn = (long long)uni((unsigned long long)B.W), st0 = (long long)uni((unsigned long long)B.step0);
     long long bi = (long long)uni((unsigned long long)B.burn_in);
     sample_walker<R>(P, S, Wn, w, st0, nsteps, bi, L, lane);

@@ -112,6 +112,8 @@ def lib():
             "scqmc_batch_sample": ([P, i64], C.c_int),
             "scqmc_batch_set_schedule": ([P, i32, i32], C.c_int),
             "scqmc_batch_set_queue": ([P, i32], C.c_int),
+            "scqmc_batch_set_kernel": ([P, i32, i32], C.c_int),
+            "scqmc_batch_get_kernel": ([P, C.POINTER(i32), C.POINTER(i32)], C.c_int),
             "scqmc_batch_tune": ([P, i64, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(dbl)], C.c_int),
         }
         for name, (args, res) in sig.items():
@@ -397,6 +399,14 @@ class Batch:
 
     def set_queue(self, bin_slots):
         self._check(lib().scqmc_batch_set_queue(self.h, int(bin_slots)))
+
+    def set_kernel(self, walkers_per_group, waves_per_simd):
+        self._check(lib().scqmc_batch_set_kernel(self.h, int(walkers_per_group), int(waves_per_simd)))
+
+    def get_kernel(self):
+        a, b = C.c_int32(), C.c_int32()
+        self._check(lib().scqmc_batch_get_kernel(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def tune(self, trial_steps):
         """Returns (order, steps_per_launch, ms_per_step); the chosen hand-out

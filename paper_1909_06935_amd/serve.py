@@ -103,10 +103,12 @@ class Server:
                          prob.seed_walk)
         return prob, eng
 
-    def run(self, requests: List[dict], realtime: bool = True, progress=None) -> List[Result]:
+    def run(self, requests: List[dict], realtime: bool = True, progress=None, on_retire=None) -> List[Result]:
         """Serve the requests (sorted by arrival).  realtime=False admits a
         request as soon as it fits, ignoring its arrival time (tests).
-        progress(finished, active, waiting, t) is called when requests retire."""
+        progress(finished, active, waiting, t) is called when requests retire;
+        on_retire(request id, engine) just before a retired request's context
+        is released (to read its walkers or sums)."""
         waiting = sorted(requests, key=lambda r: r["arrival"])
         results = {r["id"]: Result(id=r["id"], arrival=r["arrival"]) for r in requests}
         active = {}            # id -> (engine, footprint, steps)
@@ -162,6 +164,8 @@ class Server:
                 batch = None
                 for rid in done:
                     eng, fp, _ = active.pop(rid)
+                    if on_retire:
+                        on_retire(rid, eng)
                     eng.close()
                     used -= fp
         return [results[r["id"]] for r in requests]

@@ -354,18 +354,20 @@ def make_batch_systems(n_systems: int = 64, seed: int = 4001):
     return out
 
 
-def make_scan_requests(n_requests: int = 100, rate: float = 4.0, n_templates: int = 8, seed: int = 5001):
+def make_scan_requests(n_requests: int = 100, rate: float = 4.0, n_templates: int = 8, seed: int = 5001,
+                       max_orb: int = 80, max_dets: int = 20000):
     """Potential-energy-scan requests for the serving loop: Poisson arrivals
     (exponential gaps of mean 1/rate seconds); each request is one of
-    n_templates systems of the batched-form recipe (at most 40 orbitals and
-    2,000 reference determinants, so that a request solves in seconds) at a
-    geometry parameter lam ~ U[0, 1]: h1(lam) = h1 + lam D1 and
-    B(lam) = B + lam D2 with fixed random symmetric D1, D2 (N(0, 0.02))
-    per template.  Returns (templates, requests); a request is a dict with
-    id, arrival time, template index, lam and its own walker seed."""
+    n_templates systems of the batched-form recipe (20-80 orbitals,
+    CAS(4,4)-CAS(12,12), 100-20,000 reference determinants; max_orb /
+    max_dets narrow the pool) at a geometry parameter lam ~ U[0, 1]:
+    h1(lam) = h1 + lam D1 and B(lam) = B + lam D2 with fixed random
+    symmetric D1, D2 (N(0, 0.02)) per template.  Returns (templates,
+    requests); a request is a dict with id, arrival time, template index, lam
+    and its own walker seed."""
     rng = np.random.Generator(np.random.PCG64(seed))
     pool = [p for p in make_batch_systems(48, seed=seed + 1)
-            if p.space.n_orb <= 40 and len(p.ref_coeff) <= 2000][:n_templates]
+            if p.space.n_orb <= max_orb and len(p.ref_coeff) <= max_dets][:n_templates]
     templates = []
     for k, p in enumerate(pool):
         n = p.space.n_orb
@@ -394,3 +396,83 @@ def scan_problem(template, lam: float, seed_walk: int) -> Problem:
     return Problem(name=p.name, space=p.space, h1=p.h1 + lam * d1, chol=p.chol + lam * d2, e_const=0.0,
                    ref_dets=p.ref_dets, ref_coeff=p.ref_coeff, c0=p.c0, c_cls=p.c_cls,
                    n_walkers=p.n_walkers, n_steps=0, burn_in=0, seed_walk=seed_walk)
+
+
+# ---------------------------------------------------------------------------
+# problem specifications (JSON) and problem files (.npz)
+# ---------------------------------------------------------------------------
+
+def problem_from_spec(spec: dict) -> Problem:
+    """Build a problem from a JSON-able specification of its generator and
+    seeds.  Kinds:
+      {"kind": "named", "name": "cfg1" | "cfg2" | "cfg3"}
+      {"kind": "tiny", "n_core", "n_act", "n_virt", "act_a", "act_b", "seed",
+       optional "rank" (6), "ref_fraction" (1.0)}
+      {"kind": "batch", "index", optional "n_systems" (64), "seed" (4001)}
+      {"kind": "scan", "request", optional "n_requests" (100), "rate" (4.0),
+       "n_templates" (8), "seed" (5001), "max_orb" (80), "max_dets" (20000)}
+    Optional "walkers" overrides the walker count."""
+    kind = spec.get("kind")
+    if kind == "named":
+        p = make_problem(spec["name"])
+    elif kind == "tiny":
+        sp = tiny_space(int(spec["n_core"]), int(spec["n_act"]), int(spec["n_virt"]), int(spec["act_a"]),
+                        int(spec["act_b"]))
+        p = make_tiny_problem(sp, int(spec["seed"]), rank=int(spec.get("rank", 6)),
+                              ref_fraction=float(spec.get("ref_fraction", 1.0)))
+    elif kind == "batch":
+        p = make_batch_systems(int(spec.get("n_systems", 64)), seed=int(spec.get("seed", 4001)))[int(spec["index"])]
+    elif kind == "scan":
+        tpl, reqs = make_scan_requests(int(spec.get("n_requests", 100)), float(spec.get("rate", 4.0)),
+                                       int(spec.get("n_templates", 8)), int(spec.get("seed", 5001)),
+                                       int(spec.get("max_orb", 80)), int(spec.get("max_dets", 20000)))
+        r = reqs[int(spec["request"])]
+        p = scan_problem(tpl[r["template"]], r["lam"], r["seed"])
+    else:
+        raise ValueError(f"unknown problem kind {kind!r}")
+    if "walkers" in spec:
+        p.n_walkers = int(spec["walkers"])
+    return p
+
+
+_SPACE_FIELDS = ("n_orb", "n_core", "n_act", "n_elec_a", "n_elec_b")
+_SCALAR_FIELDS = ("e_const", "c0", "n_walkers", "n_steps", "burn_in", "seed_walk")
+
+
+def save_problem(path: str, prob: Problem, spec: Optional[dict] = None) -> None:
+    """Write a problem to an .npz file (arrays and scalars; the spec, if
+    given, as JSON text).  Plain arrays only: loading executes nothing."""
+    import json
+    arrays = dict(h1=prob.h1, chol=prob.chol, ref_dets=prob.ref_dets, ref_coeff=prob.ref_coeff, c_cls=prob.c_cls,
+                  space=np.array([getattr(prob.space, f) for f in _SPACE_FIELDS], dtype=np.int64),
+                  scalars=np.array([float(getattr(prob, f)) for f in _SCALAR_FIELDS]),
+                  name=np.array(prob.name), spec=np.array(json.dumps(spec or {})))
+    if prob.eps_virt is not None:
+        arrays["eps_virt"] = prob.eps_virt
+    if prob.e0_ref is not None:
+        arrays["e0_ref"] = np.array(float(prob.e0_ref))
+    np.savez(path, **arrays)
+
+
+def load_problem(path: str) -> Problem:
+    """Read a problem written by save_problem (allow_pickle stays off)."""
+    z = np.load(path, allow_pickle=False)
+    sp = Space(*[int(x) for x in z["space"]])
+    sc = dict(zip(_SCALAR_FIELDS, [float(x) for x in z["scalars"]]))
+    return Problem(name=str(z["name"]), space=sp, h1=z["h1"], chol=z["chol"], e_const=sc["e_const"],
+                   ref_dets=z["ref_dets"].astype(np.uint64), ref_coeff=z["ref_coeff"], c0=sc["c0"],
+                   c_cls=z["c_cls"], eps_virt=z["eps_virt"] if "eps_virt" in z else None,
+                   e0_ref=float(z["e0_ref"]) if "e0_ref" in z else None, n_walkers=int(sc["n_walkers"]),
+                   n_steps=int(sc["n_steps"]), burn_in=int(sc["burn_in"]), seed_walk=int(sc["seed_walk"]))
+
+
+if __name__ == "__main__":
+    # python -m paper_1909_06935_amd.workloads spec.json problem.npz
+    import json
+    import sys as _sys
+    if len(_sys.argv) != 3:
+        print("usage: python -m paper_1909_06935_amd.workloads SPEC.json OUT.npz", file=_sys.stderr)
+        _sys.exit(2)
+    with open(_sys.argv[1]) as f:
+        spec_ = json.load(f)
+    save_problem(_sys.argv[2], problem_from_spec(spec_), spec_)
