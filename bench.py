@@ -282,7 +282,9 @@ def main():
     }
     if not args.no_cpu:
         orc, idx, cb = cpu_baseline(prob, dets, prob.seed_walk, int(steps))
-        per_bytes, per_flops, nsamp = algorithmic_work(orc, dets[idx])
+        # operand count on its own seeded sample of 256 equilibrated walkers
+        sel = np.random.Generator(np.random.PCG64(314)).choice(len(dets), size=min(256, len(dets)), replace=False)
+        per_bytes, per_flops, nsamp = algorithmic_work(orc, dets[sel])
         per_launch = per_bytes * W * args.block
         avg_s = float(np.mean(launch_ms)) * 1e-3
         ach = per_launch / avg_s / 1e9
