@@ -19,10 +19,21 @@
 #define SCQ_EMPTY_KEY 0xFFFFFFFFFFFFFFFFull
 #define SCQ_NOVIRT 0xFFFFu
 
+// Hash table of the reference: open addressing, 16-byte slots.  In the
+// determinant table (key = active occupation) slot.y holds the coefficient
+// itself; in the one- / two-electron-removed tables slot.y = count << 32 |
+// offset of the key's list in `ents`.  A list entry is one 16-byte record:
+// the reference coefficient times the parity of removing the electron(s) from
+// that reference determinant, and the code of the removed electron(s) (t, or
+// t << 6 | u) -- one load per entry, and a short list in one cache line.
+struct __attribute__((aligned(16))) ListEnt {
+    double val;
+    unsigned code, pad;
+};
+
 struct DevTable {
-    const ulonglong2 *slots;         // [cap]: .x key (SCQ_EMPTY_KEY = free), .y = count << 32 | offset
-    const uint32_t *codes;           // entry codes (ytab: t; xtab: t<<6 | u; ref: 0)
-    const double *vals;              // entry reference coefficients
+    const ulonglong2 *slots;         // [cap]: .x key (SCQ_EMPTY_KEY = free)
+    const ListEnt *ents;             // list entries (removed-electron tables only)
     unsigned long long mask;         // cap - 1 (cap a power of two)
 };
 
@@ -69,6 +80,18 @@ __device__ __forceinline__ uint2 table_find(const DevTable &t, unsigned long lon
         ulonglong2 s = t.slots[slot];
         if (s.x == key) return make_uint2((unsigned)s.y, (unsigned)(s.y >> 32));
         if (s.x == SCQ_EMPTY_KEY) return make_uint2(0u, 0u);
+        slot = (slot + 1u) & m;
+    }
+}
+
+// coefficient phi0(key) from the determinant table (0 when absent)
+__device__ __forceinline__ double ref_coef(const DevTable &t, unsigned long long key) {
+    unsigned m = (unsigned)t.mask;
+    unsigned slot = (unsigned)scq_hash(key) & m;
+    while (true) {
+        ulonglong2 s = t.slots[slot];
+        if (s.x == key) return __longlong_as_double((long long)s.y);
+        if (s.x == SCQ_EMPTY_KEY) return 0.0;
         slot = (slot + 1u) & m;
     }
 }

@@ -36,13 +36,12 @@ struct DBuf {
 };
 
 struct TableBufs {
-    DBuf slots, codes, vals;
+    DBuf slots, ents;
     unsigned long long cap = 0, unique = 0;
     DevTable view() const {
         DevTable t;
         t.slots = slots.as<ulonglong2>();
-        t.codes = codes.as<uint32_t>();
-        t.vals = vals.as<double>();
+        t.ents = ents.as<ListEnt>();
         t.mask = cap ? cap - 1 : 0;
         return t;
     }
@@ -390,11 +389,13 @@ scqmc_status scqmc_set_integrals_dense(scqmc_ctx *c, const double *h1, const dou
     return SCQMC_OK;
 }
 
-// Multimap from 64-bit keys to lists of (code, coefficient), built on the
-// device: expand the reference determinants into (key, payload) pairs, count
-// distinct keys in a scratch table, insert into a table of 4x that many
-// 16-byte slots (load <= 1/4), give every key a contiguous range, scatter the
-// payloads, sort each list (deterministic content order).
+// Multimap from 64-bit keys to lists of (signed coefficient, code), built on
+// the device: expand the reference determinants into (key, payload) pairs,
+// count distinct keys in a scratch table, insert into a table of at least 4x
+// that many 16-byte slots (load <= 1/4), give every key a contiguous range,
+// scatter the payloads, sort each list (deterministic content order).  Mode 0
+// (the determinant table) keeps each key's coefficient in its slot and has no
+// entry array.
 static scqmc_status build_table(scqmc_ctx *c, int mode, const DBuf &rkeys, long long n, TableBufs &t) {
     int ne = c->nea + c->neb;
     long long per = mode == 0 ? 1 : mode == 1 ? ne : (long long)ne * (ne - 1) / 2;
@@ -439,8 +440,7 @@ static scqmc_status build_table(scqmc_ctx *c, int mode, const DBuf &rkeys, long 
     TRY(dalloc(c, tmp, sizeof(unsigned long long) * M));
     TRY(dalloc(c, total, sizeof(unsigned)));
     TRY(dalloc(c, t.slots, sizeof(ulonglong2) * cap));
-    TRY(dalloc(c, t.codes, sizeof(unsigned) * M));
-    TRY(dalloc(c, t.vals, sizeof(double) * M));
+    if (mode != 0) TRY(dalloc(c, t.ents, sizeof(ListEnt) * M));
     hipLaunchKernelGGL(k_fill_slots, dim3(grid1(cap, 256)), dim3(256), 0, st, t.slots.as<ulonglong2>(), (long long)cap);
     hipLaunchKernelGGL(k_fill_u32, dim3(grid1(cap, 256)), dim3(256), 0, st, cnt.as<unsigned>(), (long long)cap, 0u);
     hipLaunchKernelGGL(k_fill_u32, dim3(grid1(cap, 256)), dim3(256), 0, st, cur.as<unsigned>(), (long long)cap, 0u);
@@ -457,7 +457,7 @@ static scqmc_status build_table(scqmc_ctx *c, int mode, const DBuf &rkeys, long 
                            tmp.as<unsigned long long>());
     hipLaunchKernelGGL(k_finish, dim3(grid1(cap, 256)), dim3(256), 0, st, cnt.as<unsigned>(), off.as<unsigned>(),
                        (long long)cap, tmp.as<unsigned long long>(), c->refcoef.as<double>(), t.slots.as<ulonglong2>(),
-                       t.codes.as<unsigned>(), t.vals.as<double>());
+                       mode != 0 ? t.ents.as<ListEnt>() : (ListEnt *)nullptr);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(st));
     return SCQMC_OK;

@@ -37,9 +37,8 @@ __global__ void k_ref_rdm1(DevProblem P, const unsigned long long *keys, const d
                 hol &= hol - 1u;
                 int ct = 32 * sg + t;
                 unsigned long long k2 = k1 | (1ull << ct);
-                uint2 f = table_find(P.ref, k2);
-                if (!f.y) continue;
-                double ca = P.ref.vals[f.x];
+                double ca = ref_coef(P.ref, k2);
+                if (ca == 0.0) continue;
                 int e = su + key_below(k1, ct);
                 fx_add(acc + 2 * ((long long)t * A + u), (e & 1) ? -ca * cb : ca * cb);
             }

@@ -130,12 +130,18 @@ __global__ void k_scatter(const unsigned *slot_of, const unsigned long long *epa
     tmp[pos] = epay[j];
 }
 
-// sort each list by payload (deterministic content order) and write codes / coefficients
+// sort each list by payload (deterministic content order) and write the
+// entries (signed coefficient, code); the determinant table (ents == null)
+// keeps the coefficient in the slot instead (one determinant per key)
 __global__ void k_finish(const unsigned *cnt, const unsigned *off, long long cap, unsigned long long *tmp,
-                         const double *coeff, ulonglong2 *slots, unsigned *codes, double *vals) {
+                         const double *coeff, ulonglong2 *slots, ListEnt *ents) {
     long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= cap) return;
     unsigned c = cnt[s], o = off[s];
+    if (!ents) {
+        slots[s].y = c ? (unsigned long long)__double_as_longlong(coeff[tmp[o] >> 13]) : 0ull;
+        return;
+    }
     slots[s].y = ((unsigned long long)c << 32) | (unsigned long long)o;
     for (unsigned i = 1; i < c; i++) {
         unsigned long long v = tmp[o + i];
@@ -145,8 +151,11 @@ __global__ void k_finish(const unsigned *cnt, const unsigned *off, long long cap
     }
     for (unsigned i = 0; i < c; i++) {
         unsigned long long v = tmp[o + i];
-        codes[o + i] = (unsigned)(v & 0xFFFull);
-        vals[o + i] = ((v >> 12) & 1ull) ? -coeff[v >> 13] : coeff[v >> 13];
+        ListEnt e;
+        e.val = ((v >> 12) & 1ull) ? -coeff[v >> 13] : coeff[v >> 13];
+        e.code = (unsigned)(v & 0xFFFull);
+        e.pad = 0u;
+        ents[o + i] = e;
     }
 }
 

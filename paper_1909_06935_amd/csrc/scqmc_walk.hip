@@ -66,6 +66,24 @@ __device__ __forceinline__ T tload(const T *p, unsigned i) {
     return p[i];
 }
 
+// a list entry (16 bytes): scalar loads of its two fields when the index is
+// wave-uniform, one 16-byte vector load otherwise
+template <bool U>
+__device__ __forceinline__ ListEnt ent_load(const ListEnt *p, unsigned i) {
+    ListEnt e;
+    if (U) {
+        const __attribute__((address_space(4))) double *v = (const __attribute__((address_space(4))) double *)(p + i);
+        const __attribute__((address_space(4))) unsigned *c =
+            (const __attribute__((address_space(4))) unsigned *)(p + i);
+        e.val = v[0];
+        e.code = c[2];
+        e.pad = 0u;
+    } else {
+        e = p[i];
+    }
+    return e;
+}
+
 struct WaveLDS {
     GroupInfo *G;          // [65]; slot 64 holds the selected group
     uint2 *lst;            // [65 * NL]
@@ -233,8 +251,7 @@ __device__ void group_setup(const DevProblem &P, const WalkerCtx &W, const WaveL
     G.nl = 0;
     int vp = b.vp[0] + b.vp[1];
     if (vp == 0) {
-        uint2 oc = table_find(P.ref, x);
-        G.phi = oc.y ? P.ref.vals[oc.x] : 0.0;
+        G.phi = ref_coef(P.ref, x);
         G.live = G.phi != 0.0;
     } else if (vp == 2) {
         lst[0] = table_find(P.xtab, x);
@@ -387,8 +404,8 @@ __device__ double phi1(const DevProblem &P, unsigned long long y, int s, int sg,
     double acc1 = 0.0;
     uint2 oc = lists(0);
     for (unsigned k = 0; k < oc.y; k++) {
-        int t = (int)tload<U>(P.ytab.codes, oc.x + k);
-        acc1 += tload<U>(P.ytab.vals, oc.x + k) * fock(g_of_active(P, t), gs);
+        ListEnt e = ent_load<U>(P.ytab.ents, oc.x + k);
+        acc1 += e.val * fock(g_of_active(P, (int)e.code), gs);
     }
     double acc = ((bs - 1) & 1) ? -acc1 : acc1;
     // Doubles {t,u} -> {s, r}.  With Q1 < Q2 the sorted pair, the element is
@@ -410,13 +427,15 @@ __device__ double phi1(const DevProblem &P, unsigned long long y, int s, int sg,
     // alpha.  So e = bs + (electrons of y below r) + [s alpha, r beta] mod 2.
     // (The part of the phase that depends on d alone is folded into the
     // stored coefficient.)
-    // With a wave-uniform group (U) the list entries are scalars: the
-    // integrals of eight entries are requested before any is used, so their
-    // loads overlap.  Same order of additions as one entry at a time.
+    // A list is taken in masked batches (eight entries with a wave-uniform
+    // group U, whose entries are scalars; four in the lane path, where each
+    // lane has its own group): the loads of a batch's entries, and then of
+    // their integrals, are in flight together.  Same order of additions as
+    // one entry at a time.
     unsigned Np = (unsigned)P.Np, N2 = Np * Np, N3 = N2 * Np;
     unsigned sp = (unsigned)g_idx(P, gs);
     const R *E = Ints<R>::eri(P);
-    constexpr int P1UNR = (U ? 8 : 1);
+    constexpr int B = (U ? 8 : 4);
     for (int li = 1; li <= nl; li++) {
         uint2 ox = lists(li);
         unsigned cnt = ox.y & 0xFFFFFFu;
@@ -427,42 +446,33 @@ __device__ double phi1(const DevProblem &P, unsigned long long y, int s, int sg,
         R jsign = (sg == sr) ? R(-1) : R(1);
         bool neg = ((bs + key_below(y, r) + (sg == 0 && sr == 1)) & 1) != 0;
         const R *Er = E + (unsigned)(r & 31) * N2 + sp;
-        unsigned k = 0;
-        if (P1UNR > 1) {
-            for (; k + P1UNR <= cnt; k += P1UNR) {
-                unsigned cd[P1UNR];
-                double wv[P1UNR];
-                R Jv[P1UNR], Kv[P1UNR];
+        for (unsigned k = 0; k < cnt; k += B) {
+            ListEnt ev[B];
+            R Jv[B], Kv[B];
 #pragma unroll
-                for (int j = 0; j < P1UNR; j++) {
-                    cd[j] = tload<U>(P.xtab.codes, ox.x + k + j);
-                    wv[j] = tload<U>(P.xtab.vals, ox.x + k + j);
-                }
-#pragma unroll
-                for (int j = 0; j < P1UNR; j++) {
-                    unsigned q1 = (cd[j] >> 6) & 31u, q2 = cd[j] & 31u;
-                    Jv[j] = needJ ? Er[q2 * N3 + q1 * Np] : R(0);
-                    Kv[j] = needK ? Er[q1 * N3 + q2 * Np] : R(0);
-                }
-#pragma unroll
-                for (int j = 0; j < P1UNR; j++) {
-                    int t = (int)(cd[j] >> 6), u = (int)(cd[j] & 63u);
-                    if (t == r || u == r) continue;   // a single y -> y + u, summed with the y-list
-                    double el = (double)(Kv[j] + jsign * Jv[j]);
-                    acc += neg ? -wv[j] * el : wv[j] * el;
+            for (int j = 0; j < B; j++) {
+                if (k + j < cnt) {
+                    ev[j] = ent_load<U>(P.xtab.ents, ox.x + k + j);
+                } else {
+                    ev[j].val = 0.0;
+                    ev[j].code = (unsigned)(r << 6 | r);   // past the end: skipped below
                 }
             }
-        }
-        for (; k < cnt; k++) {
-            unsigned code = tload<U>(P.xtab.codes, ox.x + k);
-            int t = (int)(code >> 6), u = (int)(code & 63u);
-            if (t == r || u == r) continue;
-            double w = tload<U>(P.xtab.vals, ox.x + k);
-            unsigned q1 = (unsigned)(t & 31), q2 = (unsigned)(u & 31);
-            R J = needJ ? Er[q2 * N3 + q1 * Np] : R(0);
-            R K = needK ? Er[q1 * N3 + q2 * Np] : R(0);
-            double el = (double)(K + jsign * J);
-            acc += neg ? -w * el : w * el;
+#pragma unroll
+            for (int j = 0; j < B; j++) {
+                int t = (int)(ev[j].code >> 6), u = (int)(ev[j].code & 63u);
+                bool use = t != r && u != r;
+                unsigned q1 = (unsigned)(t & 31), q2 = (unsigned)(u & 31);
+                Jv[j] = (use && needJ) ? Er[q2 * N3 + q1 * Np] : R(0);
+                Kv[j] = (use && needK) ? Er[q1 * N3 + q2 * Np] : R(0);
+            }
+#pragma unroll
+            for (int j = 0; j < B; j++) {
+                int t = (int)(ev[j].code >> 6), u = (int)(ev[j].code & 63u);
+                if (t == r || u == r) continue;   // a single y -> y + u (summed with the y-list), or past the end
+                double el = (double)(Kv[j] + jsign * Jv[j]);
+                acc += neg ? -ev[j].val * el : ev[j].val * el;
+            }
         }
     }
     return acc;
@@ -482,57 +492,36 @@ __device__ __forceinline__ double phi2(const DevProblem &P, int s1, int s2, uint
     const R *E = Ints<R>::eri(P) + (sw ? (a2 * Np) * Np + a1 : (a1 * Np) * Np + a2);
     unsigned Ct = sw ? Np : N3, Cu = sw ? N3 : Np;   // entry offset t*Ct + u*Cu of (t a1|u a2)
     double acc = 0.0;
-    // wave-uniform group: four entries' integrals in flight at a time (same
-    // order of additions)
-    constexpr int PU = (U ? 4 : 1);
-    unsigned k = 0;
-    if (sg1 != sg2) {
-        // alpha-beta pair: only (s1 t|s2 u) survives; spin part of the phase (-1)^(n_beta + 1)
-        for (; k + PU <= ox.y; k += PU) {
-            unsigned c[PU];
-            double w[PU];
-            R e[PU];
+    // masked batches of four entries whose loads, then their integrals'
+    // loads, are in flight together; same order of additions as one entry at
+    // a time
+    constexpr int B = 4;
+    bool ab = sg1 != sg2;   // alpha-beta pair: only (s1 t|s2 u) survives
+    for (unsigned k = 0; k < ox.y; k += B) {
+        ListEnt ev[B];
+        R e1[B], e2[B];
 #pragma unroll
-            for (int j = 0; j < PU; j++) {
-                c[j] = tload<U>(P.xtab.codes, ox.x + k + j);
-                w[j] = tload<U>(P.xtab.vals, ox.x + k + j);
+        for (int j = 0; j < B; j++) {
+            if (k + j < ox.y) {
+                ev[j] = ent_load<U>(P.xtab.ents, ox.x + k + j);
+            } else {
+                ev[j].val = 0.0;
+                ev[j].code = 0u;
             }
-#pragma unroll
-            for (int j = 0; j < PU; j++) e[j] = E[((c[j] >> 6) & 31u) * Ct + (c[j] & 31u) * Cu];
-#pragma unroll
-            for (int j = 0; j < PU; j++) acc += w[j] * (double)e[j];
         }
-        for (; k < ox.y; k++) {
-            unsigned code = tload<U>(P.xtab.codes, ox.x + k);
-            unsigned t = (code >> 6) & 31u, u = code & 31u;
-            acc += tload<U>(P.xtab.vals, ox.x + k) * (double)E[t * Ct + u * Cu];
+#pragma unroll
+        for (int j = 0; j < B; j++) {
+            unsigned t = (ev[j].code >> 6) & 31u, u = ev[j].code & 31u;
+            bool in = k + j < ox.y;
+            e1[j] = in ? E[t * Ct + u * Cu] : R(0);
+            e2[j] = (in && !ab) ? E[u * Ct + t * Cu] : R(0);
         }
-        return ((P.neb + 1) & 1) ? -acc : acc;
+#pragma unroll
+        for (int j = 0; j < B; j++)
+            if (k + j < ox.y) acc += ev[j].val * (double)(e1[j] - e2[j]);
     }
-    for (; k + PU <= ox.y; k += PU) {
-        unsigned c[PU];
-        double w[PU];
-        R e1[PU], e2[PU];
-#pragma unroll
-        for (int j = 0; j < PU; j++) {
-            c[j] = tload<U>(P.xtab.codes, ox.x + k + j);
-            w[j] = tload<U>(P.xtab.vals, ox.x + k + j);
-        }
-#pragma unroll
-        for (int j = 0; j < PU; j++) {
-            unsigned t = (c[j] >> 6) & 31u, u = c[j] & 31u;
-            e1[j] = E[t * Ct + u * Cu];
-            e2[j] = E[u * Ct + t * Cu];
-        }
-#pragma unroll
-        for (int j = 0; j < PU; j++) acc += w[j] * (double)(e1[j] - e2[j]);
-    }
-    for (; k < ox.y; k++) {
-        unsigned code = tload<U>(P.xtab.codes, ox.x + k);
-        unsigned t = (code >> 6) & 31u, u = code & 31u;
-        acc += tload<U>(P.xtab.vals, ox.x + k) * (double)(E[t * Ct + u * Cu] - E[u * Ct + t * Cu]);
-    }
-    return acc;
+    // alpha-beta: spin part of the phase (-1)^(n_beta + 1)
+    return (ab && ((P.neb + 1) & 1)) ? -acc : acc;
 }
 
 // psi of one determinant with its own lookups (one lane; initialisation / snapshots)
@@ -540,10 +529,7 @@ template <class R>
 __device__ double psi_direct(const DevProblem &P, unsigned long long key, unsigned virt) {
     int vcode[2] = {(int)(virt & 0xFFFFu), (int)(virt >> 16)};
     int nv = (vcode[0] != (int)SCQ_NOVIRT) + (vcode[1] != (int)SCQ_NOVIRT);
-    if (nv == 0) {
-        uint2 oc = table_find(P.ref, key);
-        return oc.y ? P.ccls[0] * P.ref.vals[oc.x] : 0.0;
-    }
+    if (nv == 0) return P.ccls[0] * ref_coef(P.ref, key);
     if (nv == 1) {
         double phi = phi1<false, R>(
             P, key, vcode[0], (int)(vcode[0] >= P.V), popc64(key),
