@@ -259,15 +259,19 @@ scqmc_status scqmc_eval_snapshot(scqmc_ctx *ctx, int64_t n, const uint64_t *d_de
  * allocate device memory or wait on the device: code under HIP graph capture,
  * tight serving loops, harnesses that forbid hipMalloc.  Same arguments and
  * results (bit for bit: the same kernels); it calls no allocator and never
- * synchronises -- everything is enqueued on the context stream.  The compacted
- * copy of the determinants lives in a fixed device array of the library (one
- * per GPU, SCQMC_NOALLOC_MAX_DETS entries of 16 B = 1 MiB, held until the
- * process ends) that every call on that GPU shares: calls that overlap on one
- * GPU (other streams, other threads, other contexts) race; serialise them.
+ * synchronises -- everything is enqueued on the context stream.  Its scratch
+ * -- the compacted copy of the determinants (SCQMC_NOALLOC_MAX_DETS entries
+ * of 16 B = 1 MiB) and the evaluation kernel's per-wave Fock tables
+ * (SCQMC_NOALLOC_FTAB_BYTES = 16 MiB; fewer waves run when a table is large)
+ * -- lives in a fixed device array of the library (one per GPU, 17 MiB, held
+ * until the process ends) that every call on that GPU shares: calls that
+ * overlap on one GPU (other streams, other threads, other contexts) race;
+ * serialise them.
  * n > SCQMC_NOALLOC_MAX_DETS -> INVALID_ARG.  In the precision form the FP32
  * integral copies must exist (any earlier sample / eval_snapshot call after
  * set_options makes them), else SCQMC_E_STATE. */
 #define SCQMC_NOALLOC_MAX_DETS 65536
+#define SCQMC_NOALLOC_FTAB_BYTES (16u << 20)
 scqmc_status scqmc_eval_snapshot_noalloc(scqmc_ctx *ctx, int64_t n, const uint64_t *d_dets, double *d_eloc,
                                          double *d_psi, double *d_gamma, double *d_eloc_dyall, int32_t *d_class);
 /* Neighbour set M(n) of one host determinant: up to cap entries of

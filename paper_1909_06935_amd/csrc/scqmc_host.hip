@@ -67,6 +67,8 @@ struct scqmc_ctx {
     double e_core = 0.0, e0_ref = 0.0;
     double tau = 0.0;   // small-norm perturber screen of SC-NEVPT2(s): classes with N_l/N_0 < tau dropped
     DBuf heff, eri, ccls, eps, refcoef, refkey;
+    DBuf wftab;   // [W][2][A][V] Fock tables of the walker kernel (scratch of each step)
+    DBuf sftab;   // Fock tables of the snapshot kernel's wave slots
     DBuf heff32, eri32;                  // precision form: FP32 copies
     long long ints_version = 0, f32_version = -1;
     std::vector<double> refcoef_h;
@@ -147,6 +149,12 @@ static DevProblem dev_problem(const scqmc_ctx *c) {
 
 static int lists_per_group(const scqmc_ctx *c) { return std::max(1, c->nea + c->neb); }
 
+// bytes of one wave's Fock table, [2][A][V] doubles
+static size_t ftab_bytes(const scqmc_ctx *c) { return sizeof(double) * 2 * (size_t)c->A * (size_t)c->V; }
+
+// wave slots of a snapshot launch (grid-stride beyond that)
+#define SCQ_EVAL_SLOTS 16384
+
 // Class sums are kept per group of consecutive walkers (group of walker w:
 // w * ncg / W), so that E^(2) gets a jackknife error like E_var.
 static long long class_groups(long long W) { return std::min<long long>(W, 16); }
@@ -207,13 +215,15 @@ extern "C" {
 // ---------------------------------------------------------------------------
 // Fixed device memory of the allocation-free snapshot entry point: the
 // compacted copy of up to SCQMC_NOALLOC_MAX_DETS determinants (active key
-// u64, virtual codes u32, valid flag i32 = 16 B each).  Each GPU holds its own
-// copy of the array for the life of the process.  Host code must never pass
+// u64, virtual codes u32, valid flag i32 = 16 B each), then the per-wave Fock
+// tables of the evaluation kernel (SCQMC_NOALLOC_FTAB_BYTES; the launch takes
+// as many wave slots as tables fit).  Each GPU holds its own copy of the array
+// for the life of the process.  Host code must never pass
 // the array's name to a kernel (on the host it is only a stand-in symbol): its
 // device address is taken once per device with hipGetSymbolAddress, at context
 // creation with that device current, and kept in scratch_dev[].
 // ---------------------------------------------------------------------------
-static __device__ __align__(256) unsigned char scratch[(size_t)SCQMC_NOALLOC_MAX_DETS * 16];
+static __device__ __align__(256) unsigned char scratch[(size_t)SCQMC_NOALLOC_MAX_DETS * 16 + SCQMC_NOALLOC_FTAB_BYTES];
 #define SCQ_MAX_DEVICES 64
 static std::mutex scratch_mu;
 static void *scratch_dev[SCQ_MAX_DEVICES];
@@ -597,7 +607,8 @@ static scqmc_status ref_energy(scqmc_ctx *c, double &e0) {
     int NL = lists_per_group(c);
     hipLaunchKernelGGL(k_eval<double>, dim3(grid1(n, WPB)), dim3(64 * WPB), kernel_lds(c), c->stream, P,
                        c->refkey.as<unsigned long long>(), virt.as<unsigned>(), valid.as<int>(), n, NL,
-                       eloc.as<double>(), (double *)nullptr, (double *)nullptr, (double *)nullptr, (int *)nullptr);
+                       eloc.as<double>(), (double *)nullptr, (double *)nullptr, (double *)nullptr, (int *)nullptr,
+                       (double *)nullptr);
     HIPCHK(c, hipGetLastError());
     std::vector<double> el(n);
     HIPCHK(c, hipMemcpyAsync(el.data(), eloc.p, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
@@ -816,6 +827,7 @@ scqmc_status scqmc_init_walkers(scqmc_ctx *c, int64_t W, const uint64_t *dets, u
     c->ncg = class_groups(W);
     TRY(dalloc(c, c->cacc, class_acc_bytes(c)));
     TRY(dalloc(c, c->bad, sizeof(unsigned long long)));
+    TRY(dalloc(c, c->wftab, ftab_bytes(c) * W));
     HIPCHK(c, hipMemcpyAsync(c->wkey.p, keys.data(), sizeof(unsigned long long) * W, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->wvirt.p, virts.data(), sizeof(unsigned) * W, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemsetAsync(c->wsum.p, 0, sizeof(double) * 3 * W, c->stream));
@@ -856,6 +868,7 @@ static scqmc_status launch_sample(scqmc_ctx *c, long long n_steps, long long bur
     S.cacc = c->cacc.as<unsigned long long>();
     S.ncg = (int)c->ncg;
     S.bad = c->bad.as<unsigned long long>();
+    S.ftab = c->wftab.as<double>();
     int NL = lists_per_group(c);
     size_t lds = kernel_lds(c);
     int *order = c->worder.as<int>();
@@ -1169,14 +1182,17 @@ scqmc_status scqmc_eval_snapshot(scqmc_ctx *c, int64_t n, const uint64_t *d_dets
     DevProblem P = dev_problem(c);
     int NL = lists_per_group(c);
     double *d_eld = (c->opt.mode == 1 && c->has_dyall) ? d_eloc_dyall : nullptr;
+    long long slots = std::min<long long>(n, SCQ_EVAL_SLOTS);
+    if (c->sftab.n < ftab_bytes(c) * slots) TRY(dalloc(c, c->sftab, ftab_bytes(c) * slots));
+    unsigned grid = grid1(slots, WPB);
     if (c->opt.precision == 1)
-        hipLaunchKernelGGL(k_eval<float>, dim3(grid1(n, WPB)), dim3(64 * WPB), kernel_lds(c), c->stream, P,
+        hipLaunchKernelGGL(k_eval<float>, dim3(grid), dim3(64 * WPB), kernel_lds(c), c->stream, P,
                            c->skey.as<unsigned long long>(), c->svirt.as<unsigned>(), c->svalid.as<int>(),
-                           (long long)n, NL, d_eloc, d_psi, d_gamma, d_eld, (int *)d_class);
+                           (long long)n, NL, d_eloc, d_psi, d_gamma, d_eld, (int *)d_class, c->sftab.as<double>());
     else
-        hipLaunchKernelGGL(k_eval<double>, dim3(grid1(n, WPB)), dim3(64 * WPB), kernel_lds(c), c->stream, P,
+        hipLaunchKernelGGL(k_eval<double>, dim3(grid), dim3(64 * WPB), kernel_lds(c), c->stream, P,
                            c->skey.as<unsigned long long>(), c->svirt.as<unsigned>(), c->svalid.as<int>(),
-                           (long long)n, NL, d_eloc, d_psi, d_gamma, d_eld, (int *)d_class);
+                           (long long)n, NL, d_eloc, d_psi, d_gamma, d_eld, (int *)d_class, c->sftab.as<double>());
     HIPCHK(c, hipGetLastError());
     if (d_eloc_dyall && !(c->opt.mode == 1 && c->has_dyall)) {
         std::vector<double> nanv(n, NAN);
@@ -1210,14 +1226,20 @@ scqmc_status scqmc_eval_snapshot_noalloc(scqmc_ctx *c, int64_t n, const uint64_t
     DevProblem P = dev_problem(c);
     int NL = lists_per_group(c);
     bool dy = c->opt.mode == 1 && c->has_dyall;
+    // wave slots: as many Fock tables as the fixed array holds (at least one:
+    // a table is at most 2 * 32 * 96 doubles), grid-stride beyond
+    double *ftab = (double *)(base + (size_t)SCQMC_NOALLOC_MAX_DETS * 16);
+    long long slots = std::min<long long>({(long long)n, (long long)SCQ_EVAL_SLOTS,
+                                           (long long)(SCQMC_NOALLOC_FTAB_BYTES / ftab_bytes(c))});
+    unsigned grid = (unsigned)std::max<long long>(1, slots / WPB);
     if (c->opt.precision == 1)
-        hipLaunchKernelGGL(k_eval<float>, dim3(grid1(n, WPB)), dim3(64 * WPB), kernel_lds(c), c->stream, P, skey,
-                           svirt, svalid, (long long)n, NL, d_eloc, d_psi, d_gamma, dy ? d_eloc_dyall : nullptr,
-                           (int *)d_class);
+        hipLaunchKernelGGL(k_eval<float>, dim3(grid), dim3(64 * WPB), kernel_lds(c), c->stream, P, skey, svirt,
+                           svalid, (long long)n, NL, d_eloc, d_psi, d_gamma, dy ? d_eloc_dyall : nullptr,
+                           (int *)d_class, ftab);
     else
-        hipLaunchKernelGGL(k_eval<double>, dim3(grid1(n, WPB)), dim3(64 * WPB), kernel_lds(c), c->stream, P, skey,
-                           svirt, svalid, (long long)n, NL, d_eloc, d_psi, d_gamma, dy ? d_eloc_dyall : nullptr,
-                           (int *)d_class);
+        hipLaunchKernelGGL(k_eval<double>, dim3(grid), dim3(64 * WPB), kernel_lds(c), c->stream, P, skey, svirt,
+                           svalid, (long long)n, NL, d_eloc, d_psi, d_gamma, dy ? d_eloc_dyall : nullptr,
+                           (int *)d_class, ftab);
     if (d_eloc_dyall && !dy)   // no Dyall energies in mode 0: NaN, filled by a kernel (no copy, no wait)
         hipLaunchKernelGGL(k_fill_u64, dim3(grid1(n, 256)), dim3(256), 0, c->stream, (unsigned long long *)d_eloc_dyall,
                            (long long)n, 0x7FF8000000000000ull);
@@ -1324,6 +1346,7 @@ scqmc_status scqmc_load_state(scqmc_ctx *c, const void *buf, int64_t len) {
     TRY(dalloc(c, c->wsum, 24 * W));
     TRY(dalloc(c, c->cacc, class_acc_bytes(c)));
     TRY(dalloc(c, c->bad, 8));
+    TRY(dalloc(c, c->wftab, ftab_bytes(c) * W));
     int64_t o = 96;
     HIPCHK(c, hipMemcpy(c->wkey.p, b + o, 8 * W, hipMemcpyHostToDevice)); o += 8 * W;
     HIPCHK(c, hipMemcpy(c->wvirt.p, b + o, 4 * W, hipMemcpyHostToDevice)); o += ((4 * W + 7) / 8) * 8;
@@ -1543,6 +1566,7 @@ scqmc_status batch_upload(scqmc_batch *b) {
         B.S.cacc = c->cacc.as<unsigned long long>();
         B.S.ncg = (int)c->ncg;
         B.S.bad = c->bad.as<unsigned long long>();
+        B.S.ftab = c->wftab.as<double>();
         B.order = c->worder.as<int>();
         B.W = c->W;
         B.step0 = c->step;

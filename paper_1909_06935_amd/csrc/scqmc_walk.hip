@@ -84,6 +84,38 @@ __device__ __forceinline__ ListEnt ent_load(const ListEnt *p, unsigned i) {
     return e;
 }
 
+// The entries of a wave-uniform group's list, one per lane (lane j holds
+// entry j), loaded by one vector load with every lane active; the overlap
+// loops then take them with readlane instead of a scalar load per entry.
+// on = false: the list has more than 64 entries (entries read one by one).
+struct VecEnts {
+    double val;
+    unsigned code;
+    unsigned n;   // entries (n > 64: not loaded, read one by one)
+};
+__device__ __forceinline__ VecEnts vec_ents_off() {
+    VecEnts v;
+    v.val = 0.0;
+    v.code = 0u;
+    v.n = ~0u;
+    return v;
+}
+// call with every lane of the wave active (ox wave-uniform)
+__device__ __forceinline__ VecEnts vec_ents_load(const ListEnt *ents, uint2 ox, int lane) {
+    VecEnts v = vec_ents_off();
+    v.n = ox.y;
+    if ((unsigned)lane < ox.y && ox.y <= 64u) {
+        v.val = ents[ox.x + lane].val;
+        v.code = ents[ox.x + lane].code;
+    }
+    return v;
+}
+__device__ __forceinline__ double readlane_d(double x, unsigned l) {
+    long long b = __double_as_longlong(x);
+    int lo = __builtin_amdgcn_readlane((int)b, (int)l), hi = __builtin_amdgcn_readlane((int)(b >> 32), (int)l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 struct WaveLDS {
     GroupInfo *G;          // [65]; slot 64 holds the selected group
     uint2 *lst;            // [65 * NL]
@@ -119,6 +151,7 @@ struct WalkerCtx {
     int vs[2];      // virtual electrons per spin
     int e[2], h[2]; // active electrons / holes per spin
     int ne, nocc;   // active electrons, all non-core electrons
+    double *ftab;   // global [2][A][V]: the walker's Fock elements (null: summed per term)
 };
 
 struct Block {
@@ -182,7 +215,7 @@ __device__ __forceinline__ int avail_virtual(const DevProblem &P, const WalkerCt
     return lo + a;
 }
 
-__device__ bool block_setup(const DevProblem &P, const WalkerCtx &W, int rk, int pk, Block &b) {
+__device__ __forceinline__ bool block_setup(const DevProblem &P, const WalkerCtx &W, int rk, int pk, Block &b) {
     int r0 = kind_a(rk), r1 = kind_b(rk), p0 = kind_a(pk), p1 = kind_b(pk);
     b.rk = rk;
     b.pk = pk;
@@ -230,7 +263,7 @@ __device__ __forceinline__ uint2 probe_from(const DevTable &t, unsigned long lon
 }
 
 // group g of block b: decode (Ra, Pa), form x_m, do the lookups of its overlap type
-__device__ void group_setup(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, const Block &b, unsigned g,
+__device__ __forceinline__ void group_setup(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, const Block &b, unsigned g,
                             GroupInfo &G, uint2 *lst) {
     unsigned ri = g / b.npk, pi = g - ri * b.npk;
     int ra0, ra1, pa0, pa1;
@@ -373,6 +406,19 @@ __device__ __forceinline__ double fock_y(const DevProblem &P, const WalkerCtx &W
                                          int r1, int p0, int p1, int gT, int gS) {
     int t = g_idx(P, gT), s = g_idx(P, gS), st = g_spin(P, gT);
     JKOff o = jk_offsets(P, t, s);
+    if (W.ftab) {
+        // the walker's element (fock_table) minus the removed, plus the added electrons
+        double v = W.ftab[(st * P.A + t) * P.V + (s - P.A)];
+        double x[4];
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            int gJ = c == 0 ? r0 : c == 1 ? r1 : c == 2 ? p0 : p1;
+            x[c] = gJ >= 0 ? (double)jk_term<R>(P, o, g_idx(P, gJ), g_spin(P, gJ) == st) : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < 4; c++) v += c < 2 ? -x[c] : x[c];
+        return v;
+    }
     double v = (double)Ints<R>::heff(P)[s * P.Np + t];
 #pragma unroll 4
     for (int i = 0; i < W.ne; i++) {
@@ -389,6 +435,31 @@ __device__ __forceinline__ double fock_y(const DevProblem &P, const WalkerCtx &W
     return v;
 }
 
+// The walker's Fock elements, for every active t and virtual a of either spin:
+//   F[sg][t][a] = h_eff[A+a][t] + sum_{j in x_n} [(A+a t|j j) - [spin j = sg] (A+a j|j t)],
+// the one-body element of an excitation t -> a with the walker's active
+// electrons as the spectators.  The single terms of an overlap (a y-list
+// entry: y = x_n - Ra + Pa as spectators) then cost one read and at most
+// four corrections instead of a sum over every electron.  Lanes run along
+// a, the last index of both integrals.  The wave reads the table back right
+// after writing it: the fence orders its stores before those loads.
+__device__ __forceinline__ void fock_table(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, int lane) {
+    int A = P.A, V = P.V, AV = A * V, tot = 2 * AV;
+    for (int idx = lane; idx < tot; idx += WAVE) {
+        int sg = idx >= AV, rem = idx - sg * AV, t = rem / V, a = rem - t * V;
+        int s = A + a;
+        JKOff o = jk_offsets(P, t, s);
+        double v = P.heff[s * P.Np + t];
+#pragma unroll 4
+        for (int i = 0; i < W.ne; i++) {
+            int gJ = L.wg[i];
+            v += (double)jk_term<double>(P, o, g_idx(P, gJ), g_spin(P, gJ) == sg);
+        }
+        W.ftab[idx] = v;
+    }
+    __threadfence_block();
+}
+
 // <m|H|phi0> for m = y + virtual s of spin sg (0 alpha, 1 beta).  Table
 // coefficients carry the part of each Slater-Condon phase that depends on the
 // reference determinant (the annihilation of its removed electrons); the rest
@@ -397,7 +468,7 @@ __device__ __forceinline__ double fock_y(const DevProblem &P, const WalkerCtx &W
 // lists(0) is the y-list of y; lists(1..nl) are x-lists of y - r with r in
 // the top byte of .y (ascending r; empty ones may be left out).
 template <bool U, class R, class ListFn, class FockFn>
-__device__ double phi1(const DevProblem &P, unsigned long long y, int s, int sg, int nl, ListFn lists,
+__device__ __forceinline__ double phi1(const DevProblem &P, unsigned long long y, int s, int sg, int nl, ListFn lists,
                        FockFn fock) {
     int gs = g_of_virtual(P, s);
     int bs = sg ? P.nea + P.neb : P.nea;   // electrons below s in any active-space determinant
@@ -484,7 +555,7 @@ __device__ double phi1(const DevProblem &P, unsigned long long y, int s, int sg,
 // orbital that changes from lane to lane (vq), as (u a2|t a1) at
 // [u][a2][t][a1]: either way the lane-varying index is the last one.
 template <bool U, class R>
-__device__ __forceinline__ double phi2(const DevProblem &P, int s1, int s2, uint2 ox, int vq) {
+__device__ __forceinline__ double phi2(const DevProblem &P, int s1, int s2, uint2 ox, int vq, const VecEnts &ve) {
     int sg1 = s1 >= P.V, sg2 = s2 >= P.V;
     unsigned Np = (unsigned)P.Np, N3 = Np * Np * Np;
     unsigned a1 = (unsigned)(P.A + s1 - sg1 * P.V), a2 = (unsigned)(P.A + s2 - sg2 * P.V);
@@ -497,6 +568,33 @@ __device__ __forceinline__ double phi2(const DevProblem &P, int s1, int s2, uint
     // a time
     constexpr int B = 4;
     bool ab = sg1 != sg2;   // alpha-beta pair: only (s1 t|s2 u) survives
+    unsigned vn = uni(ve.n);
+    if (U && vn <= 64u) {
+        constexpr int BV = 8;
+        // entries already in the lanes: broadcast a batch, then its integrals' loads in flight together
+        for (unsigned k = 0; k < vn; k += BV) {
+            unsigned cd[BV];
+            double wv[BV];
+            R e1[BV], e2[BV];
+#pragma unroll
+            for (int j = 0; j < BV; j++) {
+                unsigned src = min(k + j, 63u);
+                cd[j] = (unsigned)__builtin_amdgcn_readlane((int)ve.code, (int)src);
+                wv[j] = readlane_d(ve.val, src);
+            }
+#pragma unroll
+            for (int j = 0; j < BV; j++) {
+                unsigned t = (cd[j] >> 6) & 31u, u = cd[j] & 31u;
+                bool in = k + j < vn;
+                e1[j] = in ? E[t * Ct + u * Cu] : R(0);
+                e2[j] = (in && !ab) ? E[u * Ct + t * Cu] : R(0);
+            }
+#pragma unroll
+            for (int j = 0; j < BV; j++)
+                if (k + j < vn) acc += wv[j] * (double)(e1[j] - e2[j]);
+        }
+        return (ab && ((P.neb + 1) & 1)) ? -acc : acc;
+    }
     for (unsigned k = 0; k < ox.y; k += B) {
         ListEnt ev[B];
         R e1[B], e2[B];
@@ -551,7 +649,7 @@ __device__ double psi_direct(const DevProblem &P, unsigned long long key, unsign
         return P.ccls[class_id1(P.V, vcode[0])] * phi;
     }
     return P.ccls[class_id2(P.V, vcode[0], vcode[1])] *
-           phi2<false, R>(P, vcode[0], vcode[1], table_find(P.xtab, key), -1);
+           phi2<false, R>(P, vcode[0], vcode[1], table_find(P.xtab, key), -1, vec_ents_off());
 }
 
 // Row r of a block, independent of the group: the virtual set of m, its
@@ -684,7 +782,7 @@ __device__ __forceinline__ uint2 view_list(const GroupView &v, int k) {
 // they would carry most of the FP32 rounding of a local energy.
 template <int VP, bool U, class R>
 __device__ __forceinline__ void row_eval(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L,
-                                         const RowDec &d, const GroupView &G, RowRes &o) {
+                                         const RowDec &d, const GroupView &G, const VecEnts &ve, RowRes &o) {
     // outer excitation n -> m: removed P*, added Q* (ascending spin-orbital order)
     int Pr0 = G.rg0, Pr1 = G.rg1, Qa0 = G.pg0, Qa1 = G.pg1;
     if (Pr0 < 0) { Pr0 = d.rv0; Pr1 = d.rv1; } else if (Pr1 < 0) Pr1 = d.rv0;
@@ -721,17 +819,17 @@ __device__ __forceinline__ void row_eval(const DevProblem &P, const WalkerCtx &W
                              return fock_y<double>(P, W, L, G.rg0, G.rg1, G.pg0, G.pg1, gT, gS);
                          });
     } else {
-        phi = phi2<U, R>(P, d.Lp0, d.Lp1, view_list<U>(G, 0), d.vq);
+        phi = phi2<U, R>(P, d.Lp0, d.Lp1, view_list<U>(G, 0), d.vq, ve);
     }
     o.psi = d.c * phi;
 }
 
 template <bool U, class R>
 __device__ __forceinline__ void row_eval_any(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, int vp,
-                                             const RowDec &d, const GroupView &G, RowRes &o) {
-    if (vp == 0) row_eval<0, U, R>(P, W, L, d, G, o);
-    else if (vp == 1) row_eval<1, U, R>(P, W, L, d, G, o);
-    else row_eval<2, U, R>(P, W, L, d, G, o);
+                                             const RowDec &d, const GroupView &G, const VecEnts &ve, RowRes &o) {
+    if (vp == 0) row_eval<0, U, R>(P, W, L, d, G, ve, o);
+    else if (vp == 1) row_eval<1, U, R>(P, W, L, d, G, ve, o);
+    else row_eval<2, U, R>(P, W, L, d, G, ve, o);
 }
 
 // Sum over the 64 lanes of a wave with DPP moves (no LDS round trips):
@@ -759,7 +857,7 @@ __device__ __forceinline__ double wave_sum(double v) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-__device__ inline void walker_setup(const DevProblem &P, const WaveLDS &L, int lane, unsigned long long key,
+__device__ __forceinline__ void walker_setup(const DevProblem &P, const WaveLDS &L, int lane, unsigned long long key,
                                     unsigned virt, WalkerCtx &W) {
     key = uni(key);
     virt = uni(virt);
@@ -787,6 +885,7 @@ __device__ inline void walker_setup(const DevProblem &P, const WaveLDS &L, int l
     }
     W.ne = W.e[0] + W.e[1];
     W.nocc = W.ne + W.n.nv;
+    W.ftab = nullptr;
     __syncwarp();
     if (lane < W.e[0]) L.wg[lane] = (short)g_of_active(P, L.occ[lane]);
     else if (lane < W.ne) L.wg[lane] = (short)g_of_active(P, L.occ[32 + lane - W.e[0]]);
@@ -797,7 +896,7 @@ __device__ inline void walker_setup(const DevProblem &P, const WaveLDS &L, int l
 }
 
 // <n|H|n> (with_virt) or <n|H_0|n> (active part only), summed over lanes in a fixed tree
-__device__ inline double wave_diag(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, int lane, bool with_virt) {
+__device__ __forceinline__ double wave_diag(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, int lane, bool with_virt) {
     int n = with_virt ? W.nocc : W.ne;
     double v = 0.0;
     if (lane < n) {
@@ -857,7 +956,7 @@ __device__ __forceinline__ void subwave_rows(const DevProblem &P, const WalkerCt
             if (rv && gc < nlive) {
                 RowRes o;
                 GroupView gv = group_view<false>(L, gi);
-                row_eval_any<false, R>(P, W, L, vp, d, gv, o);
+                row_eval_any<false, R>(P, W, L, vp, d, gv, vec_ents_off(), o);
                 if (o.ok) {
                     a.E += o.hnm * o.psi;
                     v = fabs(o.psi);
@@ -880,7 +979,7 @@ __device__ __forceinline__ void subwave_rows(const DevProblem &P, const WalkerCt
 // lanes (the blocks with one virtual electron added have 75 or 76 rows:
 // 64 + 11 or 12).
 template <bool MOVE, class R>
-__device__ void sweep_block(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, int lane, const Block &b,
+__device__ __forceinline__ void sweep_block(const DevProblem &P, const WalkerCtx &W, const WaveLDS &L, int lane, const Block &b,
                             uint32_t wid, uint32_t step, bool dy, Acc &a) {
     GroupInfo &mg = L.G[lane];
     uint2 *mlst = L.lst + lane * L.NL;
@@ -918,10 +1017,12 @@ __device__ void sweep_block(const DevProblem &P, const WalkerCtx &W, const WaveL
                 for (unsigned gc = 0; gc < nlive; gc++) {
                     unsigned gi = uni((unsigned)L.perm[gc]);
                     GroupView gv = group_view<true>(L, gi);
+                    // the group's list entries into the lanes (every lane active here)
+                    VecEnts ve = vp == 2 ? vec_ents_load(P.xtab.ents, view_list<true>(gv, 0), lane) : vec_ents_off();
                     double v = 0.0;
                     if (rv) {
                         RowRes o;
-                        row_eval_any<true, R>(P, W, L, vp, d, gv, o);
+                        row_eval_any<true, R>(P, W, L, vp, d, gv, ve, o);
                         if (o.ok) {
                             a.E += o.hnm * o.psi;
                             v = fabs(o.psi);
@@ -954,10 +1055,12 @@ __device__ void sweep_block(const DevProblem &P, const WalkerCtx &W, const WaveL
 }
 
 template <bool MOVE, class R>
-__device__ void walker_eval(const DevProblem &P, const WaveLDS &L, int lane, unsigned long long key, unsigned virt,
-                            double psin, uint32_t wid, uint32_t step, EvalOut &out) {
+__device__ __forceinline__ void walker_eval(const DevProblem &P, const WaveLDS &L, int lane, unsigned long long key, unsigned virt,
+                            double psin, uint32_t wid, uint32_t step, double *ftab, EvalOut &out) {
     WalkerCtx W;
     walker_setup(P, L, lane, key, virt, W);
+    W.ftab = ftab;
+    if (ftab) fock_table(P, W, L, lane);
     double hnn = wave_diag(P, W, L, lane, true);
     bool dy = (P.mode == 1 && W.n.nv > 0);
     double hdnn = 0.0;
@@ -1011,11 +1114,12 @@ __device__ void walker_eval(const DevProblem &P, const WaveLDS &L, int lane, uns
     int bcls = 0x7fffffff;
     double bpsi = 0.0;
     unsigned bvirt = 0;
+    VecEnts sve = vp == 2 ? vec_ents_load(P.xtab.ents, view_list<true>(sgv, 0), lane) : vec_ents_off();
     for (unsigned r = lane; r < b.R; r += WAVE) {
         RowDec d;
         row_decode(P, W, b, r, d);
         RowRes o;
-        row_eval_any<true, R>(P, W, L, vp, d, sgv, o);
+        row_eval_any<true, R>(P, W, L, vp, d, sgv, sve, o);
         if (!o.ok || o.psi == 0.0) continue;
         double tau = exp_draw(P.seed, wid, step, 1u, (uint32_t)d.cls, 0u) / fabs(o.psi);
         if (tau < b2 || (tau == b2 && d.cls < bcls)) {
@@ -1075,6 +1179,7 @@ __device__ inline void fx_add(unsigned long long *slot, double x) {
 }
 
 struct WalkerArrays {
+    double *ftab;                 // [W][2][A][V] per-walker Fock elements (scratch of the step)
     unsigned long long *key;
     unsigned *virt;
     double *psi;
@@ -1102,6 +1207,7 @@ __device__ __forceinline__ void sample_walker(const DevProblem &P, const WalkerA
     double psi = S.psi[w];
     double st = S.wsum[w], ste = S.wsum[W + w], st0 = S.wsum[2 * W + w];
     long long nbad = 0;
+    double *ftab = S.ftab ? S.ftab + w * (2LL * P.A * P.V) : nullptr;
     for (int k = 0; k < nsteps; k++) {
         long long step = step0 + k;
         EvalOut o;
@@ -1115,7 +1221,7 @@ __device__ __forceinline__ void sample_walker(const DevProblem &P, const WalkerA
             psi = __shfl(pd, 0);
         }
         psi = uni(psi);
-        walker_eval<true, R>(P, L, lane, key, virt, psi, (uint32_t)w, (uint32_t)step, o);
+        walker_eval<true, R>(P, L, lane, key, virt, psi, (uint32_t)w, (uint32_t)step, ftab, o);
         bool good = o.moved && isfinite(o.eloc) && o.gamma > 0.0 && isfinite(o.gamma);
         if (!good) { nbad++; continue; }
         if (step >= burn_in) {
@@ -1403,35 +1509,41 @@ __global__ void k_batch_advance(BatchSys *sys, int nsys, int nsteps, unsigned *h
     if (s == 0 && head) *head = 0u;
 }
 
-// local energies without moving (parity / snapshots)
+// local energies without moving (parity / snapshots).  Grid-stride over the
+// determinants: wave slot q takes q, q + slots, ...; its Fock table (ftab,
+// null: none) is slot q's, so a launch needs tables for its slots only and
+// the results do not depend on the grid.
 template <class R>
 __global__ __launch_bounds__(64 * WPB, 4) void k_eval(DevProblem P, const unsigned long long *keys, const unsigned *virts,
                                                  const int *valid, long long n, int NL, double *eloc, double *psi_out,
-                                                 double *gamma, double *elocd, int *cls_out) {
+                                                 double *gamma, double *elocd, int *cls_out, double *ftab) {
     extern __shared__ unsigned char smem[];
     int wave = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
-    long long i = (long long)blockIdx.x * WPB + wave;
-    if (i >= n) return;
+    long long q = (long long)blockIdx.x * WPB + wave, nslot = (long long)gridDim.x * WPB;
     WaveLDS L = carve(smem + wave * wave_lds_bytes(NL), NL);
-    unsigned long long key = keys[i];
-    unsigned virt = virts[i];
-    int nv = ((virt & 0xFFFFu) != SCQ_NOVIRT) + ((virt >> 16) != SCQ_NOVIRT);
-    double ps = 0.0;
-    // psi(n) itself in FP64 in both forms: it divides every term of E_L
-    if (lane == 0 && valid[i]) ps = psi_direct<double>(P, key, virt);
-    ps = __shfl(ps, 0);
-    EvalOut o;
-    if (ps != 0.0) {
-        walker_eval<false, R>(P, L, lane, key, virt, ps, (uint32_t)i, 0u, o);
-    } else {
-        o.eloc = o.elocd = o.gamma = NAN;
-    }
-    if (lane == 0) {
-        if (eloc) eloc[i] = o.eloc;
-        if (psi_out) psi_out[i] = ps;
-        if (gamma) gamma[i] = o.gamma;
-        if (elocd) elocd[i] = (P.mode == 1 && nv > 0) ? o.elocd : NAN;
-        if (cls_out) cls_out[i] = valid[i] ? (int)class_of_virt(P, virt) : -1;
+    double *ft = ftab ? ftab + q * (2LL * P.A * P.V) : nullptr;
+    for (long long i = q; i < n; i += nslot) {
+        unsigned long long key = keys[i];
+        unsigned virt = virts[i];
+        int nv = ((virt & 0xFFFFu) != SCQ_NOVIRT) + ((virt >> 16) != SCQ_NOVIRT);
+        double ps = 0.0;
+        // psi(n) itself in FP64 in both forms: it divides every term of E_L
+        if (lane == 0 && valid[i]) ps = psi_direct<double>(P, key, virt);
+        ps = __shfl(ps, 0);
+        EvalOut o;
+        if (ps != 0.0) {
+            walker_eval<false, R>(P, L, lane, key, virt, ps, (uint32_t)i, 0u, ft, o);
+        } else {
+            o.eloc = o.elocd = o.gamma = NAN;
+        }
+        if (lane == 0) {
+            if (eloc) eloc[i] = o.eloc;
+            if (psi_out) psi_out[i] = ps;
+            if (gamma) gamma[i] = o.gamma;
+            if (elocd) elocd[i] = (P.mode == 1 && nv > 0) ? o.elocd : NAN;
+            if (cls_out) cls_out[i] = valid[i] ? (int)class_of_virt(P, virt) : -1;
+        }
+        __syncwarp();
     }
 }
 
@@ -1469,7 +1581,7 @@ __global__ __launch_bounds__(64) void k_neighbors(DevProblem P, unsigned long lo
                         row_decode(P, W, b, r, d);
                         RowRes o;
                         GroupView gv = group_view<false>(L, lane);
-                        row_eval_any<false, double>(P, W, L, vp, d, gv, o);
+                        row_eval_any<false, double>(P, W, L, vp, d, gv, vec_ents_off(), o);
                         if (!o.ok) continue;
                         unsigned long long pos = atomicAdd(count, 1ull);
                         if ((long long)pos < cap) {

@@ -54,13 +54,14 @@ def prepare_templates(templates, n_iter: int = 100, lr: float = 0.02, steps_per_
 
 def footprint_bytes(prob) -> int:
     """Device memory one request holds (integrals: the full N^4 block during
-    set-up and the non-core block kept; reference tables; walkers)."""
+    set-up and the non-core block kept; reference tables; walkers and their
+    per-walker Fock tables)."""
     sp = prob.space
     n, np_ = sp.n_orb, sp.n_orb - sp.n_core
     nref = len(prob.ref_coeff)
-    a = sp.n_act
+    a, v = sp.n_act, sp.n_virt
     tables = 64 * nref * (1 + a + a * (a - 1) // 2) * 2
-    walkers = 64 * prob.n_walkers
+    walkers = (64 + 16 * a * v) * prob.n_walkers
     classes = 64 * 16 * sp.n_classes
     return 8 * n ** 4 + 8 * np_ ** 4 + tables + walkers + classes
 
