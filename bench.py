@@ -176,7 +176,7 @@ def main():
     ap.add_argument("--target-err", type=float, default=1e-2, help="serve: target E_var error (Eh)")
     ap.add_argument("--max-steps", type=int, default=10000, help="serve: step cap per request")
     ap.add_argument("--no-opt", action="store_true", help="serve: keep the templates' random SC coefficients")
-    ap.add_argument("--alone-every", type=int, default=1,
+    ap.add_argument("--alone-every", type=int, default=10,
                     help="serve: walk every k-th request alone as well (plain kernel, same steps) for the comparison")
     ap.add_argument("--hbm-gib", type=int, default=64, help="serve: device memory budget for admitted requests")
     ap.add_argument("--walkers", type=int, default=0)
@@ -343,6 +343,7 @@ def run_batch(args):
     b = Batch(engines)
     b.sample(args.warmup)
     order, spl, _ = b.tune(4)
+    wpg, wps = b.get_kernel()
     K = args.steps
     t0 = time.perf_counter()
     for e in engines:
@@ -363,7 +364,8 @@ def run_batch(args):
                    "walkers": sum(p.n_walkers for p in systems)},
         "serial_plain_value": ws / serial, "speedup_vs_serial": serial / batched,
         "schedule": {"order": order, "steps_per_launch": spl,
-                     "hand_out": "hardware dispatch" if b.bin == 0 else f"persistent grid, bins of {b.bin} slots"},
+                     "hand_out": "hardware dispatch" if b.bin == 0 else f"persistent grid, bins of {b.bin} slots",
+                     "walkers_per_workgroup": wpg, "waves_per_simd": wps},
     }
     print(json.dumps(out), flush=True)
 
@@ -392,6 +394,8 @@ def run_serve(args):
                                                           file=sys.stderr, flush=True))
     wall = time.perf_counter() - t0
     lat = np.array([r.latency for r in res])
+    ext = np.array([r.latency if r.e_err <= args.target_err else
+                    (r.finished - r.admitted) * (r.e_err / args.target_err) ** 2 for r in res])
     ws = sum(r.steps * r.walkers for r in res)
     serial = 0.0
     dev = 0.0
@@ -413,12 +417,17 @@ def run_serve(args):
         "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{len(reqs)} scan requests, Poisson {args.rate}/s, {len(templates)} systems "
-                               f"(<=40 orbitals, <=2k-det references), target E_var error {args.target_err} Eh",
+                               f"(20-80 orbitals, 100-20k-det references), target E_var error {args.target_err} Eh",
                    "requests": len(reqs), "step_cap": args.max_steps,
                    "sc_coefficients": "random" if args.no_opt else "optimised once per scan (AMSGrad)"},
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                       "max": float(lat.max())},
         "reached_target": int(sum(r.e_err <= args.target_err for r in res)),
+        # requests stopped by the step cap: the walking time the target would
+        # need at the error they reached (error falls as 1/sqrt(steps))
+        "latency_to_target_extrapolated_s": {
+            "p50": float(np.percentile(ext, 50)), "p99": float(np.percentile(ext, 99)),
+            "note": "capped requests: time walked x (error reached / target)^2 (walking time only)"},
         "steps_p50": float(np.percentile([r.steps for r in res], 50)),
         "template_prep_s": float(sum(prep)),
         "achieved_err_max": float(max(r.e_err for r in res)),

@@ -87,11 +87,12 @@ __device__ __forceinline__ ListEnt ent_load(const ListEnt *p, unsigned i) {
 // The entries of a wave-uniform group's list, one per lane (lane j holds
 // entry j), loaded by one vector load with every lane active; the overlap
 // loops then take them with readlane instead of a scalar load per entry.
-// on = false: the list has more than 64 entries (entries read one by one).
+// n = ~0: the list is short (fewer than four entries) or longer than 64, and
+// its entries are read with scalar loads.
 struct VecEnts {
     double val;
     unsigned code;
-    unsigned n;   // entries (n > 64: not loaded, read one by one)
+    unsigned n;   // entries in the lanes (~0: none loaded)
 };
 __device__ __forceinline__ VecEnts vec_ents_off() {
     VecEnts v;
@@ -103,6 +104,7 @@ __device__ __forceinline__ VecEnts vec_ents_off() {
 // call with every lane of the wave active (ox wave-uniform)
 __device__ __forceinline__ VecEnts vec_ents_load(const ListEnt *ents, uint2 ox, int lane) {
     VecEnts v = vec_ents_off();
+    if (ox.y < 4u) return v;   // short lists: scalar loads cost less than the broadcast
     v.n = ox.y;
     if ((unsigned)lane < ox.y && ox.y <= 64u) {
         v.val = ents[ox.x + lane].val;
@@ -624,7 +626,7 @@ __device__ __forceinline__ double phi2(const DevProblem &P, int s1, int s2, uint
 
 // psi of one determinant with its own lookups (one lane; initialisation / snapshots)
 template <class R>
-__device__ double psi_direct(const DevProblem &P, unsigned long long key, unsigned virt) {
+__device__ __forceinline__ double psi_direct(const DevProblem &P, unsigned long long key, unsigned virt) {
     int vcode[2] = {(int)(virt & 0xFFFFu), (int)(virt >> 16)};
     int nv = (vcode[0] != (int)SCQ_NOVIRT) + (vcode[1] != (int)SCQ_NOVIRT);
     if (nv == 0) return P.ccls[0] * ref_coef(P.ref, key);
@@ -1059,8 +1061,10 @@ __device__ __forceinline__ void walker_eval(const DevProblem &P, const WaveLDS &
                             double psin, uint32_t wid, uint32_t step, double *ftab, EvalOut &out) {
     WalkerCtx W;
     walker_setup(P, L, lane, key, virt, W);
-    W.ftab = ftab;
-    if (ftab) fock_table(P, W, L, lane);
+    // the Fock table pays where single terms are many: walkers with at most one
+    // virtual electron (two-virtual walkers reach few one-virtual overlaps)
+    W.ftab = W.n.nv < 2 ? ftab : nullptr;
+    if (W.ftab) fock_table(P, W, L, lane);
     double hnn = wave_diag(P, W, L, lane, true);
     bool dy = (P.mode == 1 && W.n.nv > 0);
     double hdnn = 0.0;
