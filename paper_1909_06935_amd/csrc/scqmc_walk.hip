@@ -570,6 +570,9 @@ __device__ __forceinline__ double phi2(const DevProblem &P, int s1, int s2, uint
     // a time
     constexpr int B = 4;
     bool ab = sg1 != sg2;   // alpha-beta pair: only (s1 t|s2 u) survives
+    // a block fixes the spins of m's virtual electrons, so with a
+    // wave-uniform group (every row of the wave in one block) this is uniform
+    if (U) ab = uni((int)ab) != 0;
     unsigned vn = uni(ve.n);
     if (U && vn <= 64u) {
         constexpr int BV = 8;
@@ -582,7 +585,7 @@ __device__ __forceinline__ double phi2(const DevProblem &P, int s1, int s2, uint
             for (int j = 0; j < BV; j++) {
                 unsigned src = min(k + j, 63u);
                 cd[j] = (unsigned)__builtin_amdgcn_readlane((int)ve.code, (int)src);
-                wv[j] = readlane_d(ve.val, src);
+                wv[j] = k + j < vn ? readlane_d(ve.val, src) : 0.0;   // past the end: weight 0
             }
 #pragma unroll
             for (int j = 0; j < BV; j++) {
@@ -592,8 +595,7 @@ __device__ __forceinline__ double phi2(const DevProblem &P, int s1, int s2, uint
                 e2[j] = (in && !ab) ? E[u * Ct + t * Cu] : R(0);
             }
 #pragma unroll
-            for (int j = 0; j < BV; j++)
-                if (k + j < vn) acc += wv[j] * (double)(e1[j] - e2[j]);
+            for (int j = 0; j < BV; j++) acc += wv[j] * (double)(e1[j] - e2[j]);
         }
         return (ab && ((P.neb + 1) & 1)) ? -acc : acc;
     }
