@@ -201,6 +201,10 @@ template <> struct Ints<float> {
 // of a group differ in their virtual electrons), so neighbouring lanes read
 // neighbouring addresses and the block actually touched (e.g. (t a|u b) with
 // t, u active) stays compact instead of one cache line per element.
+// Integral indices are formed with 24-bit multiplies (full rate on the vector
+// unit, where a 32-bit multiply takes four passes): with at most 128
+// non-core orbitals (the space check of the set-up) every factor is below
+// 2^24 and every index below 2^28.
 template <class R = double>
 __device__ __forceinline__ R eri4(const DevProblem &P, int p, int q, int r, int s) {
     unsigned Np = (unsigned)P.Np;
@@ -208,7 +212,7 @@ __device__ __forceinline__ R eri4(const DevProblem &P, int p, int q, int r, int 
     int a = p, b = q, c = r, d = s;
     if (mpq > mrs) { a = r; b = s; c = p; d = q; }
     int lo = min(c, d), hi = max(c, d);
-    return Ints<R>::eri(P)[((a * Np + b) * Np + lo) * Np + hi];
+    return Ints<R>::eri(P)[__umul24(__umul24(__umul24((unsigned)a, Np) + (unsigned)b, Np) + (unsigned)lo, Np) + (unsigned)hi];
 }
 // spin-orbital chemist integral (PQ|RS)
 template <class R = double>
@@ -237,8 +241,8 @@ __device__ __forceinline__ R double_elem_x(const DevProblem &P, int P1, int P2, 
     unsigned x = (unsigned)g_idx(P, X), y = (unsigned)g_idx(P, Y), px = (unsigned)g_idx(P, PX),
              py = (unsigned)g_idx(P, PY);
     const R *E = Ints<R>::eri(P);
-    R a = (sy == spy && sx == spx) ? E[((y * Np + py) * Np + px) * Np + x] : R(0);
-    R b = (sy == spx && sx == spy) ? E[((y * Np + px) * Np + py) * Np + x] : R(0);
+    R a = (sy == spy && sx == spx) ? E[__umul24(__umul24(__umul24(y, Np) + py, Np) + px, Np) + x] : R(0);
+    R b = (sy == spx && sx == spy) ? E[__umul24(__umul24(__umul24(y, Np) + px, Np) + py, Np) + x] : R(0);
     return a - b;
 }
 

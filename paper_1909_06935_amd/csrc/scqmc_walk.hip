@@ -373,8 +373,8 @@ __device__ __forceinline__ JKOff jk_offsets(const DevProblem &P, int p, int q, i
 template <class R>
 __device__ __forceinline__ R jk_term(const DevProblem &P, const JKOff &o, int j, bool same_spin) {
     const R *E = Ints<R>::eri(P);
-    R J = E[(unsigned)j * o.cJ + o.offJ];
-    R K = same_spin ? E[(unsigned)j * o.cK + o.offK] : R(0);
+    R J = E[__umul24((unsigned)j, o.cJ) + o.offJ];
+    R K = same_spin ? E[__umul24((unsigned)j, o.cK) + o.offK] : R(0);
     return J - K;
 }
 
@@ -536,8 +536,8 @@ __device__ __forceinline__ double phi1(const DevProblem &P, unsigned long long y
                 int t = (int)(ev[j].code >> 6), u = (int)(ev[j].code & 63u);
                 bool use = t != r && u != r;
                 unsigned q1 = (unsigned)(t & 31), q2 = (unsigned)(u & 31);
-                Jv[j] = (use && needJ) ? Er[q2 * N3 + q1 * Np] : R(0);
-                Kv[j] = (use && needK) ? Er[q1 * N3 + q2 * Np] : R(0);
+                Jv[j] = (use && needJ) ? Er[__umul24(q2, N3) + __umul24(q1, Np)] : R(0);
+                Kv[j] = (use && needK) ? Er[__umul24(q1, N3) + __umul24(q2, Np)] : R(0);
             }
 #pragma unroll
             for (int j = 0; j < B; j++) {
@@ -591,8 +591,8 @@ __device__ __forceinline__ double phi2(const DevProblem &P, int s1, int s2, uint
             for (int j = 0; j < BV; j++) {
                 unsigned t = (cd[j] >> 6) & 31u, u = cd[j] & 31u;
                 bool in = k + j < vn;
-                e1[j] = in ? E[t * Ct + u * Cu] : R(0);
-                e2[j] = (in && !ab) ? E[u * Ct + t * Cu] : R(0);
+                e1[j] = in ? E[__umul24(t, Ct) + __umul24(u, Cu)] : R(0);
+                e2[j] = (in && !ab) ? E[__umul24(u, Ct) + __umul24(t, Cu)] : R(0);
             }
 #pragma unroll
             for (int j = 0; j < BV; j++) acc += wv[j] * (double)(e1[j] - e2[j]);
@@ -615,8 +615,8 @@ __device__ __forceinline__ double phi2(const DevProblem &P, int s1, int s2, uint
         for (int j = 0; j < B; j++) {
             unsigned t = (ev[j].code >> 6) & 31u, u = ev[j].code & 31u;
             bool in = k + j < ox.y;
-            e1[j] = in ? E[t * Ct + u * Cu] : R(0);
-            e2[j] = (in && !ab) ? E[u * Ct + t * Cu] : R(0);
+            e1[j] = in ? E[__umul24(t, Ct) + __umul24(u, Cu)] : R(0);
+            e2[j] = (in && !ab) ? E[__umul24(u, Ct) + __umul24(t, Cu)] : R(0);
         }
 #pragma unroll
         for (int j = 0; j < B; j++)
