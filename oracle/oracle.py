@@ -14,13 +14,18 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "scqmc_oracle.c")
-LIB = os.path.join(HERE, "liboracle.so")
+# SCQMC_ORACLE_LIB: load this prebuilt copy instead (the mutation test
+# builds deliberately broken copies and checks that the pins reject them)
+LIB_OVERRIDE = os.environ.get("SCQMC_ORACLE_LIB")
+LIB = LIB_OVERRIDE or os.path.join(HERE, "liboracle.so")
 
 _lib = None
 
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (-O2, OpenMP)."""
+    if LIB_OVERRIDE:
+        return LIB
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, SRC, "-lm"])
